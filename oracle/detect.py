@@ -1,0 +1,73 @@
+"""Reduction, detection and peak parameters (oracle).
+
+Test infrastructure only: nothing in the product path imports this module.
+
+* Reduced map: for every (coarse cell, range row) the largest power over the
+  cell's fine space and the smallest fine index attaining it (the ML estimate
+  of eq. (72) restricted to one coarse cell and row; the "maximum output of
+  each range bin" shown for Experiment 1).
+* LRT threshold (Sec. III-C, eqs. (31), (33)): |Y| > gamma with
+  gamma^2 = -M K sigma^2 ln P_FA.  The input here is the range-compressed echo,
+  whose per-sample noise variance sigma^2 already contains the K frequency
+  bins, so the threshold on power is gamma^2 = -M sigma^2 ln P_FA.
+* Detections: reduced-map entries above gamma^2, listed in flat order
+  (coarse cell major, then row); each carries its argmax fine cell.
+* Peak parameters (eq. (72), Alg. 3 with kappa = 1): r0 = n0 dr and
+  (v, a, j) = (coarse centre + fine offset) * fine step, in float64.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .grid import Grid
+from .transforms import dsgrft_cell
+
+
+def reduce_power(power: np.ndarray):
+    """Max over the last axis and the first index attaining it."""
+    return power.max(axis=-1), power.argmax(axis=-1).astype(np.int32)
+
+
+def dsgrft_reduced(echo, grid: Grid, cells=None, rows=None, chunk=1024):
+    """Reduced DS-GRFT map for the listed coarse cells.
+
+    Returns (pmax [n_cells, rows] float64, argf [n_cells, rows] int32).
+    """
+    cells = list(range(grid.n_coarse)) if cells is None else list(cells)
+    r_all = (np.arange(grid.n_begin, grid.n_end) if rows is None
+             else np.asarray(rows))
+    pm = np.empty((len(cells), len(r_all)))
+    af = np.empty((len(cells), len(r_all)), dtype=np.int32)
+    for ci, k in enumerate(cells):
+        for s in range(0, len(r_all), chunk):
+            y = dsgrft_cell(echo, grid, k, rows=r_all[s:s + chunk])
+            p, a = reduce_power(np.abs(y) ** 2)
+            pm[ci, s:s + chunk] = p
+            af[ci, s:s + chunk] = a
+    return pm, af
+
+
+def threshold(M: int, sigma2: float, pfa: float) -> float:
+    """gamma^2 on |Y|^2, eq. (33) with the K bins folded into sigma^2."""
+    return -M * sigma2 * math.log(pfa)
+
+
+def global_argmax(pmax: np.ndarray):
+    """Flat (cell, row) index of the largest reduced power, smallest on ties."""
+    flat = int(np.argmax(pmax.reshape(-1)))
+    return divmod(flat, pmax.shape[1])
+
+
+def detections(pmax: np.ndarray, argf: np.ndarray, gamma2: float):
+    """(cell, row, fine) triples with power above gamma^2, flat order."""
+    k, r = np.nonzero(pmax > gamma2)
+    return [(int(a), int(b), int(argf[a, b])) for a, b in zip(k, r)]
+
+
+def peak_params(grid: Grid, k: int, n0: int, f: int):
+    """(r0, v, a, j) in float64 for coarse cell k, range row n0, fine f."""
+    i = grid.lattice_point(k, f)
+    v, a, j = grid.params(i)
+    return n0 * grid.dr, v, a, j
