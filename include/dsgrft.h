@@ -1,0 +1,236 @@
+/*
+ * dsgrft.h -- C ABI of the MI355X dual-scale GRFT search library.
+ *
+ * Method: Li et al., "Efficient dual-scale generalized Radon-Fourier transform
+ * detector family for long time coherent integration" (arXiv 2403.06788).
+ *
+ * Problem (Sec. V-A, Alg. 3): a range-compressed complex echo s[m][n]
+ * (M pulses x N range bins), radar parameters (f_c, f_s, PRF) and motion
+ * parameter extents go in; a detection map and peak parameters come out.
+ * The search evaluates, for every coarse cell c_c of the dual-scale lattice
+ * (Sec. IV-B, eqs. (48)-(52)), the time-domain mGIFT (gather of each pulse's
+ * range bin along the coarse walk and the pre-DFM de-ramp, eqs. (46)-(47),
+ * Alg. 1) followed by the GFT over the cell's fine space (eq. (44), Alg. 2),
+ * and reduces |.|^2 over the fine space (eq. (72)).
+ *
+ * Conventions shared by every entry point
+ *  - Complex data are interleaved (re, im) pairs: complex64 = 2 x float,
+ *    complex128 = 2 x double.  The echo is row-major [M][N] complex64.
+ *  - "d_" arguments are device pointers on the current HIP device; "h_"
+ *    arguments are host pointers.  The caller owns every I/O buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work is enqueued on it; no entry point synchronises the stream
+ *    unless its comment says so.  A plan may be used by one stream at a time.
+ *  - The plan owns its device workspace, allocated in dsgrft_plan_create.
+ *    Execution entry points allocate nothing.
+ *  - Errors are reported as status codes only; nothing aborts or prints.
+ *    On any non-OK status no device work has been enqueued, except for
+ *    DSGRFT_E_DEVICE, where a HIP call failed part-way.
+ *
+ * Lattice (reading of eqs. (39)-(42) with alpha_p = 1 per order):
+ *  lambda = c/f_c, dr = c/(2 f_s), T = M/PRF, R = f_c/f_s (must be an
+ *  integer), fine steps dv = lambda/(2T), da = lambda/T^2, dj = 3 lambda/T^3
+ *  (motion r(t) = r0 + v t + a t^2/2 + j t^3/6, t_m = m/PRF, m = 0..M-1).
+ *  Axis p covers integer indices [i_lo,p, i_lo,p + K_p R) (bounds rounded
+ *  outward; within 1e-6 of a lattice point counts as on it).  Coarse cell
+ *  k = (k3 K2 + k2) K1 + k1 has centre i_c,p = i_lo,p + k_p R + R/2 (integer
+ *  division); fine index f = (u3 R + u2) R + u1, offsets u_p - R/2.
+ *  Range offsets round half up; all offsets and phases are exact integers.
+ */
+#ifndef DSGRFT_H
+#define DSGRFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSGRFT_OK = 0,
+  DSGRFT_E_INVALID = 1,      /* invalid argument (null pointer, bad size, ...) */
+  DSGRFT_E_NOMEM = 2,        /* device allocation failed (plan creation only)  */
+  DSGRFT_E_DEVICE = 3,       /* a HIP runtime call failed                      */
+  DSGRFT_E_UNSUPPORTED = 4,  /* valid request outside what is implemented      */
+  DSGRFT_E_CAPACITY = 5      /* output list too small; true count reported     */
+} dsgrft_status;
+
+/* Arithmetic of the fine search (the GFT stage).  FP32 runs on the vector
+ * ALUs; the others on MFMA with FP32 accumulation.  `split` = 1 uses one
+ * rounding of each operand; split = 3 adds the hi*lo and lo*hi correction
+ * products of a hi+lo split of both operands. */
+typedef enum {
+  DSGRFT_FORM_F32 = 0,   /* plain FP32 (speed baseline)             */
+  DSGRFT_FORM_F16 = 1,   /* fp16 x fp16 -> fp32, split 1 or 3       */
+  DSGRFT_FORM_BF16 = 2,  /* bf16 x bf16 -> fp32, split 1 or 3       */
+  DSGRFT_FORM_FP8 = 3    /* fp8 e4m3, per-row scale, split 1 or 3   */
+} dsgrft_form;
+
+typedef struct {
+  double fc;     /* carrier frequency f_c [Hz]                          */
+  double fs;     /* range sampling rate f_s [Hz]; range bin c/(2 f_s)   */
+  double prf;    /* pulse repetition frequency [Hz]                     */
+  double c;      /* propagation speed [m/s] (3e8 in the paper)          */
+  double kappa;  /* scale of Prop. 1; only 1.0 is supported             */
+} dsgrft_radar;
+
+typedef struct {
+  double min, max;  /* search extent: v [m/s], a [m/s^2], j [m/s^3] */
+} dsgrft_axis;
+
+typedef struct {
+  int32_t M;          /* pulses                                           */
+  int32_t N;          /* range bins of the echo                           */
+  int32_t order;      /* motion order P in 1..3                           */
+  int32_t n_begin;    /* first searched range row (paper's bins of        */
+  int32_t n_end;      /*   interest, Sec. IV-E); 0,0 means [0, N)         */
+  dsgrft_axis axis[3];/* extents of v, a, j (orders above P are ignored)  */
+  int32_t batch;      /* gathered units per fine-search batch; 0 = auto   */
+} dsgrft_config;
+
+typedef struct {
+  int32_t R;             /* fine cells per coarse step and order          */
+  int32_t K[3];          /* coarse cells per order (1 above P)            */
+  int32_t i_lo[3];       /* first fine lattice index per order            */
+  int32_t rows;          /* n_end - n_begin                               */
+  int64_t n_coarse;      /* K1 K2 K3                                      */
+  int64_t n_fine;        /* R^P                                           */
+  double lambda, dr, T;  /* wavelength, range bin, integration time       */
+  double step[3];        /* fine steps dv, da, dj                         */
+  size_t workspace_bytes;/* device memory held by the plan                */
+} dsgrft_plan_info;
+
+typedef struct {
+  int64_t coarse;  /* coarse cell index k                                 */
+  int32_t row;     /* range row n0 (absolute bin index)                   */
+  int32_t fine;    /* fine index f                                        */
+  float power;     /* |Y|^2 at the cell                                   */
+  float pad_;
+  double r0, v, a, j; /* eq. (72) with kappa = 1: n0 dr, lattice * steps  */
+} dsgrft_peak;
+
+typedef struct dsgrft_plan_s *dsgrft_plan;
+
+/* Plan creation: validates the radar and lattice, derives the dual-scale
+ * lattice and builds the fine phase matrix H_DFM(t_m; c_f) x velocity term
+ * (eq. (44)) for the orders 1..min(P,2) in every arithmetic form, and sizes
+ * the workspace.  E_INVALID for null pointers, M or N < 1, order outside
+ * 1..3, min > max, f_c/f_s not a positive integer, a trajectory numerator that
+ * could leave int64, or a bad row range; E_UNSUPPORTED for kappa != 1;
+ * E_NOMEM if device memory runs out.  Uses the current HIP device and
+ * synchronises it before returning. */
+dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
+                                 const dsgrft_config *cfg, dsgrft_plan *out);
+
+/* Releases the plan and its workspace (synchronises the device first).
+ * Accepts NULL. */
+void dsgrft_plan_destroy(dsgrft_plan plan);
+
+dsgrft_status dsgrft_plan_get_info(dsgrft_plan plan, dsgrft_plan_info *out);
+
+/* Static text for a status code (never NULL). */
+const char *dsgrft_status_string(dsgrft_status s);
+
+/* Coarse tables (stage a0 of the hot path): for coarse cells
+ * [cc_begin, cc_begin + n): d_off[i][m] = round-half-up walk in bins of the
+ * cell centre (mGIFT envelope correction, eq. (46)), d_psi[i][m] =
+ * exp(+j 2 pi Num/M^3), the pre-DFM phase H_pre-DFM of eq. (47), complex64.
+ * Layout [n][M].  E_INVALID if the range leaves [0, n_coarse). */
+dsgrft_status dsgrft_coarse_tables(dsgrft_plan plan, int64_t cc_begin,
+                                   int64_t n, int32_t *d_off, void *d_psi,
+                                   void *stream);
+
+/* mGIFT in the time domain (stages a1 + a2, Alg. 1): for coarse cells
+ * [cc_begin, cc_begin + n) writes y[i][m][r] = S(m, n_begin + r + off) * psi
+ * (S = 0 outside [0, N)) as complex64, layout [n][M][rows]. */
+dsgrft_status dsgrft_mgift(dsgrft_plan plan, const void *d_echo,
+                           int64_t cc_begin, int64_t n, void *d_out,
+                           void *stream);
+
+/* DS-GRFT search (stages a1..a4, Alg. 3): for each listed coarse cell and
+ * range row, the largest |Y|^2 over the cell's fine space and the smallest
+ * fine index attaining it (ties to the smaller index).  Cells are
+ * d_cells[0..n) (device int64 list) or, when d_cells is NULL,
+ * cc_begin..cc_begin+n-1.  Outputs d_pmax, d_argf: [n][rows] (float, int32).
+ * `form`/`split`: see dsgrft_form; FP32 requires split = 1.  The echo must
+ * stay unchanged until the stream reaches the end of this call. */
+dsgrft_status dsgrft_search(dsgrft_plan plan, dsgrft_form form, int32_t split,
+                            const void *d_echo, const int64_t *d_cells,
+                            int64_t cc_begin, int64_t n, float *d_pmax,
+                            int32_t *d_argf, void *stream);
+
+/* Full DS-GRFT power map |Y|^2 for coarse cells [cc_begin, cc_begin + n):
+ * d_power[n][rows][n_fine] float.  Same forms as dsgrft_search.  Intended for
+ * small plans (tests, figures); E_INVALID if the map would exceed 2^31
+ * elements. */
+dsgrft_status dsgrft_search_full(dsgrft_plan plan, dsgrft_form form,
+                                 int32_t split, const void *d_echo,
+                                 int64_t cc_begin, int64_t n, float *d_power,
+                                 void *stream);
+
+/* Single-scale TD-GRFT (Sec. III-A-1, eq. (13)) at the same lattice points,
+ * FP32: per-cell range offsets along the full walk.  d_pmax/d_argf as in
+ * dsgrft_search for cells [cc_begin, cc_begin+n); d_power ([n][rows][n_fine]
+ * float) may be NULL, otherwise it receives the full map. */
+dsgrft_status dsgrft_grft(dsgrft_plan plan, const void *d_echo,
+                          int64_t cc_begin, int64_t n, float *d_pmax,
+                          int32_t *d_argf, float *d_power, void *stream);
+
+/* Mean |s|^2 of the echo (noise power estimate for the threshold), written
+ * to d_sigma2 (one double). */
+dsgrft_status dsgrft_noise_power(dsgrft_plan plan, const void *d_echo,
+                                 double *d_sigma2, void *stream);
+
+/* LRT detection (Sec. III-C, eqs. (31), (33); Alg. 3): entries of a reduced
+ * map [n][rows] (cells cc_begin.. or d_cells as in dsgrft_search) with power
+ * > gamma2 are listed in flat order (cell, then row) into d_peaks[0..cap) with
+ * their parameters (eq. (72), kappa = 1).  *d_count receives the number of
+ * entries above the threshold (may exceed cap).  d_best receives the global
+ * maximum (smallest flat index on ties), regardless of the threshold.  For
+ * the LRT threshold use gamma2 = -M sigma^2 ln P_FA.  No status reports
+ * overflow because the count is only known on the device; compare
+ * *d_count with cap after the stream completes. */
+dsgrft_status dsgrft_detect(dsgrft_plan plan, const float *d_pmax,
+                            const int32_t *d_argf, const int64_t *d_cells,
+                            int64_t cc_begin, int64_t n, double gamma2,
+                            dsgrft_peak *d_peaks, int32_t cap,
+                            int32_t *d_count, dsgrft_peak *d_best,
+                            void *stream);
+
+/* Continuous objective for off-grid refinement (not in the paper; see the
+ * oracle for the definition): for candidates theta[b] = (r0, v, a) (device
+ * double [B][3]) computes Y_b (complex128) and J_b = |Y_b|^2 in FP64, and
+ * stores d_saved[b] = (Y, dY/dr0, dY/dv, dY/da) as 4 complex128 for the
+ * backward pass.  Orders 1 and 2 only (E_UNSUPPORTED otherwise). */
+dsgrft_status dsgrft_adjoint_forward(dsgrft_plan plan, const void *d_echo,
+                                     const double *d_theta, int32_t B,
+                                     double *d_J, double *d_saved,
+                                     void *stream);
+
+/* Backward pass: d_grad_theta[b][p] = gJ[b] * dJ_b/dtheta_p (FP64, from the
+ * saved values) and, if d_grad_echo is not NULL, d_grad_echo[m][n] =
+ * sum_b gJ[b] * 2 Y_b conj(sinc(x_bm - n) exp(j phi_bm)) as complex64
+ * (PyTorch's gradient convention for complex inputs), overwritten. */
+dsgrft_status dsgrft_adjoint_backward(dsgrft_plan plan, const void *d_echo,
+                                      const double *d_theta, int32_t B,
+                                      const double *d_saved,
+                                      const double *d_gJ,
+                                      double *d_grad_theta, void *d_grad_echo,
+                                      void *stream);
+
+/* Off-grid peak refinement: `iters` steps of per-candidate gradient ascent
+ * on J with a trust region in fine-step units (theta updated in place, final
+ * J in d_J).  Each step takes the normalised gradient direction scaled by the
+ * candidate's trust radius, accepts it if J does not decrease and doubles the
+ * radius (capped), otherwise halves the radius.  Candidates stay inside the
+ * coarse cell they started in. */
+dsgrft_status dsgrft_refine(dsgrft_plan plan, const void *d_echo,
+                            double *d_theta, int32_t B, int32_t iters,
+                            double *d_J, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSGRFT_H */

@@ -1,0 +1,413 @@
+// Continuous DS-GRFT objective, its adjoint and off-grid refinement (FP64).
+//
+// The paper defines the transforms on the search lattice only; the off-grid
+// objective is this library's reading.  For theta = (r0, v, a):
+//   coarse cell  k_p = clamp(floor((theta_p/d_p - i_lo,p + 1/2) / R)), centre i_c
+//   envelope     x_m = r0/dr + off(m; i_c)   (coarse walk, as in mGIFT)
+//   interpolant  s~_m(x) = sum_{n<N} s[m][n] sinc(x - n)
+//   phase        cyc_m = 2 (v t_m + a t_m^2/2) / lambda, range-reduced in FP64
+//   Y = sum_m s~_m(x_m) exp(j 2 pi cyc_m),  J = |Y|^2.
+// J equals the DS-GRFT power map at lattice points (sinc of an integer is a
+// Kronecker delta).  sinc(x - n) is evaluated as (-1)^(floor(x) - n)
+// sinpi(frac(x)) / (pi (x - n)), with a series near zero.
+//
+// Forward: a workgroup of 256 threads takes CB candidates; per chunk of 64
+// pulses the per-(candidate, pulse) quantities are formed once into LDS, and
+// each thread then sweeps its share of range taps for all CB candidates,
+// reusing every echo load CB times.  Accumulated per thread: Y, dY/dr0 (with
+// sinc'), sum s~ e t and sum s~ e t^2 (for dY/dv, dY/da), reduced at the end.
+#include "internal.h"
+
+namespace {
+
+constexpr int CB = 4;     // candidates per workgroup
+constexpr int MCH = 64;   // pulses per table chunk
+constexpr int TPB = 256;
+
+struct AdjCtx {
+  int M, N, P, R, K0, K1, ilo0, ilo1;
+  double dr, prf, lam, st0, st1;
+  Lat L;
+};
+
+struct Tap {   // per (candidate, pulse)
+  double xf, sp, cp, er, ei, t;
+  int xi;
+  int pad;
+};
+
+__device__ inline void centre_of(const AdjCtx &c, double v, double a, int64_t ic[2]) {
+  const double th[2] = {v, a};
+  const int K[2] = {c.K0, c.K1}, il[2] = {c.ilo0, c.ilo1};
+  const double st[2] = {c.st0, c.st1};
+  for (int p = 0; p < 2; ++p) {
+    if (p >= c.P) {
+      ic[p] = 0;
+      continue;
+    }
+    double u = th[p] / st[p];
+    double kf = floor((u - (double)il[p] + 0.5) / (double)c.R);
+    int64_t k = (int64_t)kf;
+    if (kf < 0) k = 0;
+    if (kf > K[p] - 1) k = K[p] - 1;
+    ic[p] = (int64_t)il[p] + k * c.R + c.R / 2;
+  }
+}
+
+__device__ inline Tap make_tap(const AdjCtx &c, const double *th, const int64_t *ic,
+                               int m) {
+  Tap T;
+  const int64_t num = lat_num(c.L, m, ic[0], ic[1], 0);
+  const double x = th[0] / c.dr + (double)lat_offset(c.L, num);
+  const double xi = floor(x);
+  T.xi = (int)xi;
+  T.xf = x - xi;
+  sincospi(T.xf, &T.sp, &T.cp);
+  const double t = (double)m / c.prf;
+  const double cyc = 2.0 * (th[1] * t + th[2] * t * t / 2.0) / c.lam;
+  const double fr = cyc - floor(cyc);
+  sincospi(2.0 * fr, &T.ei, &T.er);
+  T.t = t;
+  T.pad = 0;
+  return T;
+}
+
+// sinc(d) and its derivative for d = x - n with x = xi + xf.
+__device__ inline void sinc_pair(const Tap &T, int n, double &w, double &dw) {
+  const double d = (double)(T.xi - n) + T.xf;
+  const double sg = ((T.xi - n) & 1) ? -1.0 : 1.0;
+  if (fabs(d) < 1e-4) {
+    const double pd = M_PI * d;
+    w = 1.0 - pd * pd / 6.0;
+    dw = -(M_PI * M_PI) * d / 3.0 + (M_PI * M_PI * M_PI * M_PI) * d * d * d / 30.0;
+  } else {
+    const double r = 1.0 / d;
+    w = sg * T.sp * r * (1.0 / M_PI);
+    dw = (sg * T.cp - w) * r;
+  }
+}
+
+__device__ inline double block_sum(double v, double *red) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < TPB / 64; ++w) s += red[w];
+  return s;
+}
+
+// Computes, for candidates th[0..CB), the 8 complex sums (Y, dY/dr0, sum s~ e t,
+// sum s~ e t^2) into out[CB][8] (all threads receive them).
+__device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
+                           const double (*th)[3], int nb, double (*out)[8],
+                           Tap *s_tap, double *red) {
+  int64_t ic[CB][2];
+  for (int b = 0; b < CB; ++b) {
+    if (b < nb) centre_of(c, th[b][1], th[b][2], ic[b]);
+    else ic[b][0] = ic[b][1] = 0;
+  }
+  double acc[CB][8];
+  for (int b = 0; b < CB; ++b)
+    for (int q = 0; q < 8; ++q) acc[b][q] = 0.0;
+  const int tid = threadIdx.x;
+  for (int m0 = 0; m0 < c.M; m0 += MCH) {
+    __syncthreads();
+    {
+      const int b = tid / MCH, mm = tid % MCH;   // CB * MCH == TPB
+      const int m = m0 + mm;
+      if (b < nb && m < c.M) s_tap[tid] = make_tap(c, th[b], ic[b], m);
+    }
+    __syncthreads();
+    const int mend = (c.M - m0) < MCH ? (c.M - m0) : MCH;
+    for (int mm = 0; mm < mend; ++mm) {
+      const float2 *row = echo + (int64_t)(m0 + mm) * c.N;
+      double sr[CB], si[CB], dr_[CB], di[CB];
+      for (int b = 0; b < CB; ++b) sr[b] = si[b] = dr_[b] = di[b] = 0.0;
+      for (int n = tid; n < c.N; n += TPB) {
+        const float2 s = row[n];
+        for (int b = 0; b < CB; ++b) {
+          if (b >= nb) break;
+          double w, dw;
+          sinc_pair(s_tap[b * MCH + mm], n, w, dw);
+          sr[b] = fma((double)s.x, w, sr[b]);
+          si[b] = fma((double)s.y, w, si[b]);
+          dr_[b] = fma((double)s.x, dw, dr_[b]);
+          di[b] = fma((double)s.y, dw, di[b]);
+        }
+      }
+      for (int b = 0; b < CB; ++b) {
+        if (b >= nb) break;
+        const Tap &T = s_tap[b * MCH + mm];
+        // (sr + j si) * (er + j ei)
+        const double yr = sr[b] * T.er - si[b] * T.ei;
+        const double yi = sr[b] * T.ei + si[b] * T.er;
+        const double gr = dr_[b] * T.er - di[b] * T.ei;
+        const double gi = dr_[b] * T.ei + di[b] * T.er;
+        acc[b][0] += yr;
+        acc[b][1] += yi;
+        acc[b][2] += gr;
+        acc[b][3] += gi;
+        acc[b][4] += yr * T.t;
+        acc[b][5] += yi * T.t;
+        acc[b][6] += yr * T.t * T.t;
+        acc[b][7] += yi * T.t * T.t;
+      }
+    }
+  }
+  for (int b = 0; b < CB; ++b)
+    for (int q = 0; q < 8; ++q) out[b][q] = block_sum(acc[b][q], red);
+}
+
+// saved[b] = (Y, dY/dr0, dY/dv, dY/da) as complex128
+__device__ inline void finish(const AdjCtx &c, const double *o, double *sv) {
+  sv[0] = o[0];
+  sv[1] = o[1];
+  sv[2] = o[2] / c.dr;
+  sv[3] = o[3] / c.dr;
+  // dY/dv = j 2 pi (2/lambda) sum s~ e t ; j (x + j y) = -y + j x
+  const double kv = 2.0 * M_PI * 2.0 / c.lam, ka = 2.0 * M_PI / c.lam;
+  sv[4] = -kv * o[5];
+  sv[5] = kv * o[4];
+  sv[6] = -ka * o[7];
+  sv[7] = ka * o[6];
+}
+
+__global__ __launch_bounds__(TPB) void k_adj_fwd(AdjCtx c, const float2 *__restrict__ echo,
+                                                 const double *__restrict__ theta, int B,
+                                                 double *__restrict__ J,
+                                                 double *__restrict__ saved) {
+  __shared__ Tap s_tap[TPB];
+  __shared__ double red[TPB / 64];
+  const int b0 = blockIdx.x * CB;
+  const int nb = (B - b0) < CB ? (B - b0) : CB;
+  double th[CB][3];
+  for (int b = 0; b < CB; ++b)
+    for (int q = 0; q < 3; ++q) th[b][q] = (b < nb) ? theta[(b0 + b) * 3 + q] : 0.0;
+  double out[CB][8];
+  eval_block(c, echo, th, nb, out, s_tap, red);
+  if (threadIdx.x == 0) {
+    for (int b = 0; b < nb; ++b) {
+      double sv[8];
+      finish(c, out[b], sv);
+      J[b0 + b] = sv[0] * sv[0] + sv[1] * sv[1];
+      if (saved)
+        for (int q = 0; q < 8; ++q) saved[(int64_t)(b0 + b) * 8 + q] = sv[q];
+    }
+  }
+}
+
+__global__ void k_adj_theta(const double *__restrict__ saved,
+                            const double *__restrict__ gJ, int B,
+                            double *__restrict__ gt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const double *s = saved + (int64_t)b * 8;
+  const double g = gJ ? gJ[b] : 1.0;
+  for (int p = 0; p < 3; ++p)  // dJ = 2 Re(conj(Y) dY)
+    gt[b * 3 + p] = g * 2.0 * (s[0] * s[2 + 2 * p] + s[1] * s[3 + 2 * p]);
+}
+
+struct BTap {  // per candidate for one pulse: sinc data and 2 gJ Y conj(e)
+  double xf, sp, cr, ci;
+  int xi;
+  int pad;
+};
+
+// grad_s[m][n] = sum_b sinc(x_bm - n) * (2 gJ_b Y_b conj(e_bm)).  One
+// workgroup per (pulse, 2048-bin slab); the candidate loop is chunked through
+// LDS.
+__global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__restrict__ theta,
+                                                  int B, const double *__restrict__ saved,
+                                                  const double *__restrict__ gJ,
+                                                  float2 *__restrict__ ge) {
+  __shared__ BTap s_b[TPB];
+  constexpr int PER = 8;
+  const int slabs = (c.N + TPB * PER - 1) / (TPB * PER);
+  const int m = blockIdx.x / slabs;
+  const int n0 = (blockIdx.x % slabs) * TPB * PER;
+  const int tid = threadIdx.x;
+  double ar[PER], ai[PER];
+  for (int q = 0; q < PER; ++q) ar[q] = ai[q] = 0.0;
+  for (int bb = 0; bb < B; bb += TPB) {
+    __syncthreads();
+    const int b = bb + tid;
+    if (b < B) {
+      double th[3] = {theta[b * 3], theta[b * 3 + 1], theta[b * 3 + 2]};
+      int64_t ic[2];
+      centre_of(c, th[1], th[2], ic);
+      Tap T = make_tap(c, th, ic, m);
+      const double g = 2.0 * (gJ ? gJ[b] : 1.0);
+      const double yr = saved[(int64_t)b * 8], yi = saved[(int64_t)b * 8 + 1];
+      // 2 gJ Y conj(e)
+      BTap q;
+      q.xf = T.xf;
+      q.sp = T.sp;
+      q.xi = T.xi;
+      q.pad = 0;
+      q.cr = g * (yr * T.er + yi * T.ei);
+      q.ci = g * (yi * T.er - yr * T.ei);
+      s_b[tid] = q;
+    }
+    __syncthreads();
+    const int bend = (B - bb) < TPB ? (B - bb) : TPB;
+    for (int k = 0; k < bend; ++k) {
+      const BTap q = s_b[k];
+      Tap T;
+      T.xf = q.xf;
+      T.sp = q.sp;
+      T.cp = 0.0;
+      T.xi = q.xi;
+      for (int e = 0; e < PER; ++e) {
+        const int n = n0 + tid + TPB * e;
+        const double d = (double)(q.xi - n) + q.xf;
+        double w;
+        if (fabs(d) < 1e-4) {
+          const double pd = M_PI * d;
+          w = 1.0 - pd * pd / 6.0;
+        } else {
+          const double sg = ((q.xi - n) & 1) ? -1.0 : 1.0;
+          w = sg * q.sp / (M_PI * d);
+        }
+        ar[e] = fma(w, q.cr, ar[e]);
+        ai[e] = fma(w, q.ci, ai[e]);
+      }
+    }
+  }
+  for (int e = 0; e < PER; ++e) {
+    const int n = n0 + tid + TPB * e;
+    if (n < c.N) ge[(int64_t)m * c.N + n] = make_float2((float)ar[e], (float)ai[e]);
+  }
+}
+
+// Refinement: per candidate, normalised-gradient steps with a trust radius in
+// (range bin, fine velocity step, fine acceleration step) units; a step is
+// kept if J does not decrease (radius doubled, at most 2), otherwise the
+// radius is halved.  The fine indices stay inside the starting coarse cell,
+// r0 inside [0, N-1] bins.
+__global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restrict__ echo,
+                                                double *__restrict__ theta, int B, int iters,
+                                                double *__restrict__ Jout) {
+  __shared__ Tap s_tap[TPB];
+  __shared__ double red[TPB / 64];
+  const int b0 = blockIdx.x * CB;
+  const int nb = (B - b0) < CB ? (B - b0) : CB;
+  double th[CB][3], lo[CB][3], hi[CB][3], rho[CB], J[CB];
+  const double sc[3] = {c.dr, c.st0, c.st1};
+  for (int b = 0; b < CB; ++b) {
+    for (int q = 0; q < 3; ++q) th[b][q] = (b < nb) ? theta[(b0 + b) * 3 + q] : 0.0;
+    int64_t ic[2];
+    centre_of(c, th[b][1], th[b][2], ic);
+    lo[b][0] = 0.0;
+    hi[b][0] = (double)(c.N - 1) * c.dr;
+    for (int p = 0; p < 2; ++p) {
+      if (p < c.P) {
+        // continuous fine index range of the coarse cell, kept 1e-6 inside
+        const double ulo = (double)(ic[p] - c.R / 2) - 0.5 + 1e-6;
+        const double uhi = (double)(ic[p] - c.R / 2 + c.R) - 0.5 - 1e-6;
+        lo[b][1 + p] = ulo * sc[1 + p];
+        hi[b][1 + p] = uhi * sc[1 + p];
+      } else {
+        lo[b][1 + p] = hi[b][1 + p] = 0.0;
+      }
+    }
+    for (int q = 0; q < 3; ++q) th[b][q] = fmin(fmax(th[b][q], lo[b][q]), hi[b][q]);
+    rho[b] = 0.5;
+  }
+  double out[CB][8], sv[CB][8];
+  eval_block(c, echo, th, nb, out, s_tap, red);
+  for (int b = 0; b < nb; ++b) {
+    finish(c, out[b], sv[b]);
+    J[b] = sv[b][0] * sv[b][0] + sv[b][1] * sv[b][1];
+  }
+  for (int it = 0; it < iters; ++it) {
+    double prop[CB][3];
+    for (int b = 0; b < CB; ++b) {
+      double g[3], gn = 0.0;
+      for (int p = 0; p < 3; ++p) {
+        g[p] = (b < nb) ? 2.0 * (sv[b][0] * sv[b][2 + 2 * p] + sv[b][1] * sv[b][3 + 2 * p]) * sc[p]
+                        : 0.0;
+        gn += g[p] * g[p];
+      }
+      gn = sqrt(gn);
+      for (int p = 0; p < 3; ++p) {
+        const double z = (gn > 0.0) ? th[b][p] + rho[b] * g[p] / gn * sc[p] : th[b][p];
+        prop[b][p] = fmin(fmax(z, lo[b][p]), hi[b][p]);
+      }
+    }
+    double po[CB][8];
+    eval_block(c, echo, prop, nb, po, s_tap, red);
+    for (int b = 0; b < nb; ++b) {
+      double ps[8];
+      finish(c, po[b], ps);
+      const double Jp = ps[0] * ps[0] + ps[1] * ps[1];
+      if (Jp >= J[b]) {
+        for (int p = 0; p < 3; ++p) th[b][p] = prop[b][p];
+        for (int q = 0; q < 8; ++q) sv[b][q] = ps[q];
+        J[b] = Jp;
+        rho[b] = fmin(2.0 * rho[b], 2.0);
+      } else {
+        rho[b] *= 0.5;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int b = 0; b < nb; ++b) {
+      for (int q = 0; q < 3; ++q) theta[(b0 + b) * 3 + q] = th[b][q];
+      if (Jout) Jout[b0 + b] = J[b];
+    }
+  }
+}
+
+AdjCtx make_ctx(dsgrft_plan p) {
+  AdjCtx c;
+  c.M = p->M;
+  c.N = p->N;
+  c.P = p->P;
+  c.R = p->R;
+  c.K0 = p->K[0];
+  c.K1 = p->K[1];
+  c.ilo0 = p->ilo[0];
+  c.ilo1 = p->ilo[1];
+  c.dr = p->dr;
+  c.prf = p->radar.prf;
+  c.lam = p->lam;
+  c.st0 = p->step[0];
+  c.st1 = p->step[1];
+  c.L = p->lat;
+  return c;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_forward(dsgrft_plan p, const float2 *echo,
+                                  const double *theta, int B, double *J,
+                                  double *saved, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_fwd, dim3((B + CB - 1) / CB), dim3(TPB), 0, s, make_ctx(p),
+                     echo, theta, B, J, saved);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_backward(dsgrft_plan p, const float2 *echo,
+                                   const double *theta, int B,
+                                   const double *saved, const double *gJ,
+                                   double *grad_theta, float2 *grad_echo,
+                                   hipStream_t s) {
+  (void)echo;
+  if (grad_theta)
+    hipLaunchKernelGGL(k_adj_theta, dim3((B + 255) / 256), dim3(256), 0, s, saved, gJ,
+                       B, grad_theta);
+  if (grad_echo) {
+    const int slabs = (p->N + TPB * 8 - 1) / (TPB * 8);
+    hipLaunchKernelGGL(k_adj_echo, dim3((unsigned)(p->M * slabs)), dim3(TPB), 0, s,
+                       make_ctx(p), theta, B, saved, gJ, grad_echo);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_refine(dsgrft_plan p, const float2 *echo, double *theta, int B,
+                         int iters, double *J, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine, dim3((B + CB - 1) / CB), dim3(TPB), 0, s, make_ctx(p),
+                     echo, theta, B, iters, J);
+  return hipGetLastError();
+}

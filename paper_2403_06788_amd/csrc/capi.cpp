@@ -1,0 +1,423 @@
+// C ABI of the DS-GRFT library: plan construction (lattice derivation,
+// validation, workspace sizing, fine tables) and the stream-ordered entry
+// points that sequence the kernels.  See include/dsgrft.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace {
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Nearest integer when x lies within tol of it; sets ok accordingly.
+long long snap(double x, double tol, bool &ok) {
+  double r = std::nearbyint(x);
+  ok = std::fabs(x - r) <= tol;
+  return (long long)r;
+}
+
+// Outward-rounded index bounds of [lo, hi] on the lattice i * step; a bound
+// within 1e-6 of a lattice point counts as on it.
+void index_bounds(double lo, double hi, double step, long long &il, long long &ih) {
+  bool ok;
+  double xl = lo / step, xh = hi / step;
+  long long s = snap(xl, 1e-6, ok);
+  il = ok ? s : (long long)std::floor(xl);
+  s = snap(xh, 1e-6, ok);
+  ih = ok ? s : (long long)std::ceil(xh);
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t bytes, size_t &total) {
+  *p = nullptr;
+  if (bytes == 0) return hipSuccess;
+  hipError_t e = hipMalloc((void **)p, bytes);
+  if (e == hipSuccess) total += bytes;
+  return e;
+}
+
+void release(dsgrft_plan p) {
+  if (!p) return;
+  void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->u_off, p->u_psi,
+                  p->G, p->g_scale, p->packed, p->det_ws, p->adj_ws};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+bool on_plan_device(dsgrft_plan p) {
+  int d = -1;
+  return hipGetDevice(&d) == hipSuccess && d == p->device;
+}
+
+dsgrft_status check_form(dsgrft_form form, int split) {
+  switch (form) {
+    case DSGRFT_FORM_F32:
+      return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
+    case DSGRFT_FORM_F16:
+    case DSGRFT_FORM_BF16:
+      return (split == 1 || split == 3) ? DSGRFT_OK : DSGRFT_E_INVALID;
+    case DSGRFT_FORM_FP8:
+      return (split == 1 || split == 3) ? DSGRFT_E_UNSUPPORTED : DSGRFT_E_INVALID;
+    default:
+      return DSGRFT_E_INVALID;
+  }
+}
+
+// Stages a0..a4 over n listed cells, batch by batch.  pmax/argf may be NULL
+// (full-map only), full may be NULL.
+dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
+                         const float2 *echo, const int64_t *cells,
+                         int64_t cc_begin, int64_t n, float *pmax, int32_t *argf,
+                         float *full, hipStream_t s) {
+  const int64_t Bc = p->batch_cells, Bu = p->batch_units;
+  for (int64_t c0 = 0; c0 < n; c0 += Bc) {
+    const int64_t nc = (n - c0) < Bc ? (n - c0) : Bc;
+    DS_TRY(launch_fill_u64(p->packed, nc * p->rows, s));
+    const int64_t nut = nc * p->R3;
+    const int64_t *cl = cells ? cells + c0 : nullptr;
+    float *fl = full ? full + c0 * p->rows * p->n_fine : nullptr;
+    for (int64_t u0 = 0; u0 < nut; u0 += Bu) {
+      const int64_t nu = (nut - u0) < Bu ? (nut - u0) : Bu;
+      DS_TRY(launch_unit_tables(p, cl, cc_begin + c0, u0, nu, s));
+      if (form == DSGRFT_FORM_F32) {
+        DS_TRY(launch_gather_f32(p, echo, nu, s));
+        DS_TRY(launch_fine_f32(p, nu, u0, fl, 0, s));
+      } else {
+        DS_TRY(launch_gather_lp(p, form, split, echo, nu, s));
+        DS_TRY(launch_fine_mfma(p, form, split, nu, u0, fl, s));
+      }
+    }
+    if (pmax && argf)
+      DS_TRY(launch_unpack(p, nc, pmax + c0 * p->rows, argf + c0 * p->rows, s));
+  }
+  return DSGRFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dsgrft_status_string(dsgrft_status s) {
+  switch (s) {
+    case DSGRFT_OK: return "ok";
+    case DSGRFT_E_INVALID: return "invalid argument";
+    case DSGRFT_E_NOMEM: return "out of device memory";
+    case DSGRFT_E_DEVICE: return "HIP runtime error";
+    case DSGRFT_E_UNSUPPORTED: return "unsupported request";
+    case DSGRFT_E_CAPACITY: return "output capacity exceeded";
+    default: return "unknown status";
+  }
+}
+
+dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
+                                 const dsgrft_config *cfg, dsgrft_plan *out) {
+  if (!radar || !cfg || !out) return DSGRFT_E_INVALID;
+  *out = nullptr;
+  if (!finite_pos(radar->fc) || !finite_pos(radar->fs) ||
+      !finite_pos(radar->prf) || !finite_pos(radar->c))
+    return DSGRFT_E_INVALID;
+  if (!std::isfinite(radar->kappa)) return DSGRFT_E_INVALID;
+  if (radar->kappa != 1.0) return DSGRFT_E_UNSUPPORTED;
+  const int M = cfg->M, N = cfg->N, P = cfg->order;
+  if (M < 1 || N < 1 || P < 1 || P > 3 || cfg->batch < 0) return DSGRFT_E_INVALID;
+  if (M > (1 << 20) || N > (1 << 28)) return DSGRFT_E_INVALID;
+  int nb = cfg->n_begin, ne = cfg->n_end;
+  if (nb == 0 && ne == 0) ne = N;
+  if (nb < 0 || nb >= ne || ne > N) return DSGRFT_E_INVALID;
+  const double ratio = radar->fc / radar->fs;
+  bool ok;
+  const long long R = snap(ratio, 1e-9 * (ratio > 1.0 ? ratio : 1.0), ok);
+  if (!ok || R < 1 || R > 4096) return DSGRFT_E_INVALID;
+
+  dsgrft_plan p = new (std::nothrow) dsgrft_plan_s();
+  if (!p) return DSGRFT_E_NOMEM;
+  p->radar = *radar;
+  p->cfg = *cfg;
+  p->M = M;
+  p->N = N;
+  p->P = P;
+  p->n_begin = nb;
+  p->n_end = ne;
+  p->rows = ne - nb;
+  p->R = (int)R;
+  p->h = (int)(R / 2);
+  p->lam = radar->c / radar->fc;
+  p->dr = radar->c / (2.0 * radar->fs);
+  p->T = M / radar->prf;
+  p->step[0] = p->lam / (2.0 * p->T);
+  p->step[1] = p->lam / (p->T * p->T);
+  p->step[2] = 3.0 * p->lam / (p->T * p->T * p->T);
+  // lattice per order
+  __int128 bound = 0;
+  const __int128 M3 = (__int128)M * M * M;
+  for (int q = 0; q < 3; ++q) {
+    if (q < P) {
+      const dsgrft_axis &ax = cfg->axis[q];
+      if (!std::isfinite(ax.min) || !std::isfinite(ax.max) || ax.min > ax.max) {
+        delete p;
+        return DSGRFT_E_INVALID;
+      }
+      const double xl = ax.min / p->step[q], xh = ax.max / p->step[q];
+      if (std::fabs(xl) > 1e15 || std::fabs(xh) > 1e15) {
+        delete p;
+        return DSGRFT_E_INVALID;
+      }
+      long long il, ih;
+      index_bounds(ax.min, ax.max, p->step[q], il, ih);
+      const long long Kq = (ih - il + 1 + R - 1) / R;
+      const long long top = il + Kq * R;
+      if (il < -(1LL << 30) || top > (1LL << 30) || Kq > (1LL << 30)) {
+        delete p;
+        return DSGRFT_E_INVALID;
+      }
+      p->ilo[q] = (int)il;
+      p->K[q] = (int)Kq;
+      const long long mag = (il < 0 ? -il : il) > (top < 0 ? -top : top)
+                                ? (il < 0 ? -il : il)
+                                : (top < 0 ? -top : top);
+      bound += (__int128)mag * M3;
+    } else {
+      p->ilo[q] = 0;
+      p->K[q] = 1;
+    }
+  }
+  if (2 * bound + (__int128)R * M3 >= ((__int128)1 << 62)) {
+    delete p;
+    return DSGRFT_E_INVALID;
+  }
+  p->lat.M = M;
+  p->lat.M3 = (int64_t)M3;
+  p->lat.RM3 = (int64_t)(R * M3);
+  p->n_coarse = (int64_t)p->K[0] * p->K[1] * p->K[2];
+  long long nf = 1, C = 1;
+  for (int q = 0; q < P; ++q) nf *= R;
+  for (int q = 0; q < (P < 2 ? P : 2); ++q) C *= R;
+  if (nf >= 0xffffffffLL) {
+    delete p;
+    return DSGRFT_E_INVALID;
+  }
+  p->n_fine = nf;
+  p->C = (int)C;
+  p->R3 = (P == 3) ? (int)R : 1;
+  // padded sizes
+  p->Mp = (M + KTILE - 1) / KTILE * KTILE;
+  p->rows_p = (p->rows + ROWTILE - 1) / ROWTILE * ROWTILE;
+  p->Cp = (p->C + COLTILE - 1) / COLTILE * COLTILE;
+  p->KB = p->Mp / 16;
+  p->NB = p->rows_p / 32;
+  p->FB = p->Cp / 32;
+  // batching: gathered units of at most ~512 MiB at 8 bytes per sample
+  const size_t per_unit = (size_t)p->rows_p * p->Mp * 8;
+  const int64_t total_units = p->n_coarse * p->R3;
+  int64_t bu = cfg->batch > 0 ? cfg->batch : (int64_t)((512ull << 20) / per_unit);
+  if (bu < 1) bu = 1;
+  if (bu > total_units) bu = total_units;
+  if (p->R3 > 1) {
+    if (bu >= p->R3) {
+      p->batch_cells = bu / p->R3;
+      bu = p->batch_cells * p->R3;
+    } else {
+      p->batch_cells = 1;
+    }
+  } else {
+    p->batch_cells = bu;
+  }
+  p->batch_units = bu;
+
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return DSGRFT_E_DEVICE;
+  }
+  size_t tot = 0;
+  const size_t f16b = (size_t)4 * p->Cp * p->Mp * 2;
+  p->det_ws_bytes = detect_ws_bytes(p->n_coarse * (int64_t)p->rows);
+  const int64_t noise_parts = ((int64_t)M * N + 65535) / 65536;
+  p->adj_ws_bytes = (size_t)(noise_parts + 64) * sizeof(double);
+  if (dalloc(&p->F32, (size_t)p->Mp * p->Cp * sizeof(float2), tot) != hipSuccess ||
+      dalloc(&p->F16, f16b, tot) != hipSuccess ||
+      dalloc(&p->FBF16, f16b, tot) != hipSuccess ||
+      dalloc(&p->u_off, (size_t)bu * p->Mp * sizeof(int32_t), tot) != hipSuccess ||
+      dalloc(&p->u_psi, (size_t)bu * p->Mp * sizeof(float2), tot) != hipSuccess ||
+      dalloc((char **)&p->G, (size_t)bu * per_unit, tot) != hipSuccess ||
+      dalloc(&p->packed, (size_t)p->batch_cells * p->rows * 8, tot) != hipSuccess ||
+      dalloc((char **)&p->det_ws, p->det_ws_bytes, tot) != hipSuccess ||
+      dalloc(&p->adj_ws, p->adj_ws_bytes, tot) != hipSuccess) {
+    (void)hipGetLastError();
+    release(p);
+    return DSGRFT_E_NOMEM;
+  }
+  p->ws_bytes = tot;
+  if (launch_fine_tables(p, nullptr) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    release(p);
+    return DSGRFT_E_DEVICE;
+  }
+  *out = p;
+  return DSGRFT_OK;
+}
+
+void dsgrft_plan_destroy(dsgrft_plan plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  release(plan);
+}
+
+dsgrft_status dsgrft_plan_get_info(dsgrft_plan p, dsgrft_plan_info *o) {
+  if (!p || !o) return DSGRFT_E_INVALID;
+  o->R = p->R;
+  for (int q = 0; q < 3; ++q) {
+    o->K[q] = p->K[q];
+    o->i_lo[q] = p->ilo[q];
+    o->step[q] = p->step[q];
+  }
+  o->rows = p->rows;
+  o->n_coarse = p->n_coarse;
+  o->n_fine = p->n_fine;
+  o->lambda = p->lam;
+  o->dr = p->dr;
+  o->T = p->T;
+  o->workspace_bytes = p->ws_bytes;
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_coarse_tables(dsgrft_plan p, int64_t cc_begin, int64_t n,
+                                   int32_t *d_off, void *d_psi, void *stream) {
+  if (!p || !d_off || !d_psi || n < 1 || cc_begin < 0 || cc_begin + n > p->n_coarse)
+    return DSGRFT_E_INVALID;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  DS_TRY(launch_coarse_tables(p, cc_begin, n, p->M, d_off, (float2 *)d_psi,
+                              (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_mgift(dsgrft_plan p, const void *d_echo, int64_t cc_begin,
+                           int64_t n, void *d_out, void *stream) {
+  if (!p || !d_echo || !d_out || n < 1 || cc_begin < 0 || cc_begin + n > p->n_coarse)
+    return DSGRFT_E_INVALID;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t c0 = 0; c0 < n; c0 += p->batch_units) {
+    const int64_t nc = (n - c0) < p->batch_units ? (n - c0) : p->batch_units;
+    DS_TRY(launch_coarse_tables(p, cc_begin + c0, nc, p->Mp, p->u_off, p->u_psi, s));
+    DS_TRY(launch_mgift_out(p, (const float2 *)d_echo, nc,
+                            (float2 *)d_out + c0 * (int64_t)p->M * p->rows, s));
+  }
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_search(dsgrft_plan p, dsgrft_form form, int32_t split,
+                            const void *d_echo, const int64_t *d_cells,
+                            int64_t cc_begin, int64_t n, float *d_pmax,
+                            int32_t *d_argf, void *stream) {
+  if (!p || !d_echo || !d_pmax || !d_argf || n < 1) return DSGRFT_E_INVALID;
+  if (!d_cells && (cc_begin < 0 || cc_begin + n > p->n_coarse)) return DSGRFT_E_INVALID;
+  dsgrft_status st = check_form(form, split);
+  if (st != DSGRFT_OK) return st;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  return run_search(p, form, split, (const float2 *)d_echo, d_cells, cc_begin, n,
+                    d_pmax, d_argf, nullptr, (hipStream_t)stream);
+}
+
+dsgrft_status dsgrft_search_full(dsgrft_plan p, dsgrft_form form, int32_t split,
+                                 const void *d_echo, int64_t cc_begin, int64_t n,
+                                 float *d_power, void *stream) {
+  if (!p || !d_echo || !d_power || n < 1 || cc_begin < 0 || cc_begin + n > p->n_coarse)
+    return DSGRFT_E_INVALID;
+  if ((double)n * p->rows * (double)p->n_fine > 2147483647.0) return DSGRFT_E_INVALID;
+  dsgrft_status st = check_form(form, split);
+  if (st != DSGRFT_OK) return st;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  return run_search(p, form, split, (const float2 *)d_echo, nullptr, cc_begin, n,
+                    nullptr, nullptr, d_power, (hipStream_t)stream);
+}
+
+dsgrft_status dsgrft_grft(dsgrft_plan p, const void *d_echo, int64_t cc_begin,
+                          int64_t n, float *d_pmax, int32_t *d_argf, float *d_power,
+                          void *stream) {
+  if (!p || !d_echo || n < 1 || cc_begin < 0 || cc_begin + n > p->n_coarse)
+    return DSGRFT_E_INVALID;
+  if ((d_pmax == nullptr) != (d_argf == nullptr)) return DSGRFT_E_INVALID;
+  if (!d_pmax && !d_power) return DSGRFT_E_INVALID;
+  if (d_power && (double)n * p->rows * (double)p->n_fine > 2147483647.0)
+    return DSGRFT_E_INVALID;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  const float2 *echo = (const float2 *)d_echo;
+  for (int64_t c0 = 0; c0 < n; c0 += p->batch_cells) {
+    const int64_t nc = (n - c0) < p->batch_cells ? (n - c0) : p->batch_cells;
+    DS_TRY(launch_fill_u64(p->packed, nc * p->rows, s));
+    DS_TRY(launch_grft(p, echo, cc_begin + c0, nc,
+                       d_power ? d_power + c0 * p->rows * p->n_fine : nullptr, s));
+    if (d_pmax)
+      DS_TRY(launch_unpack(p, nc, d_pmax + c0 * p->rows, d_argf + c0 * p->rows, s));
+  }
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_noise_power(dsgrft_plan p, const void *d_echo, double *d_sigma2,
+                                 void *stream) {
+  if (!p || !d_echo || !d_sigma2) return DSGRFT_E_INVALID;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  DS_TRY(launch_noise_power(p, (const float2 *)d_echo, d_sigma2, (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_detect(dsgrft_plan p, const float *d_pmax, const int32_t *d_argf,
+                            const int64_t *d_cells, int64_t cc_begin, int64_t n,
+                            double gamma2, dsgrft_peak *d_peaks, int32_t cap,
+                            int32_t *d_count, dsgrft_peak *d_best, void *stream) {
+  if (!p || !d_pmax || !d_argf || !d_count || n < 1 || cap < 0) return DSGRFT_E_INVALID;
+  if (cap > 0 && !d_peaks) return DSGRFT_E_INVALID;
+  if (!std::isfinite(gamma2) && !std::isinf(gamma2)) return DSGRFT_E_INVALID;
+  if (!d_cells && (cc_begin < 0 || cc_begin + n > p->n_coarse)) return DSGRFT_E_INVALID;
+  if (n > p->n_coarse || (double)n * p->rows > 2147483647.0) return DSGRFT_E_INVALID;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  DS_TRY(launch_detect(p, d_pmax, d_argf, d_cells, cc_begin, n, gamma2, d_peaks, cap,
+                       d_count, d_best, (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_adjoint_forward(dsgrft_plan p, const void *d_echo,
+                                     const double *d_theta, int32_t B, double *d_J,
+                                     double *d_saved, void *stream) {
+  if (!p || !d_echo || !d_theta || !d_J || B < 1) return DSGRFT_E_INVALID;
+  if (p->P > 2) return DSGRFT_E_UNSUPPORTED;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  DS_TRY(launch_adjoint_forward(p, (const float2 *)d_echo, d_theta, B, d_J, d_saved,
+                                (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_adjoint_backward(dsgrft_plan p, const void *d_echo,
+                                      const double *d_theta, int32_t B,
+                                      const double *d_saved, const double *d_gJ,
+                                      double *d_grad_theta, void *d_grad_echo,
+                                      void *stream) {
+  if (!p || !d_echo || !d_theta || !d_saved || !d_gJ || B < 1) return DSGRFT_E_INVALID;
+  if (!d_grad_theta && !d_grad_echo) return DSGRFT_E_INVALID;
+  if (p->P > 2) return DSGRFT_E_UNSUPPORTED;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  DS_TRY(launch_adjoint_backward(p, (const float2 *)d_echo, d_theta, B, d_saved, d_gJ,
+                                 d_grad_theta, (float2 *)d_grad_echo,
+                                 (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_refine(dsgrft_plan p, const void *d_echo, double *d_theta,
+                            int32_t B, int32_t iters, double *d_J, void *stream) {
+  if (!p || !d_echo || !d_theta || !d_J || B < 1 || iters < 0 || iters > 10000)
+    return DSGRFT_E_INVALID;
+  if (p->P > 2) return DSGRFT_E_UNSUPPORTED;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  DS_TRY(launch_refine(p, (const float2 *)d_echo, d_theta, B, iters, d_J,
+                       (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
+}  // extern "C"

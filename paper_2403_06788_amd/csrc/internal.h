@@ -1,0 +1,160 @@
+// Internal declarations of the DS-GRFT library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dsgrft.h"
+
+// ---------------------------------------------------------------------------
+// Exact lattice arithmetic, shared by host plan code and device kernels.
+//
+// With integer fine-lattice indices i = (i1, i2, i3) and t_m = m / PRF:
+//   2 D(t_m) / lambda = Num / M^3,  D(t_m) / dr = Num / (R M^3),
+//   Num(m; i) = i1 m M^2 + i2 m^2 M + i3 m^3.
+// The range offset is round-half-up of Num / (R M^3) and the phase is
+// exp(+j 2 pi (Num mod M^3) / M^3), both from exact integers.
+// ---------------------------------------------------------------------------
+struct Lat {
+  int64_t M, M3, RM3;  // M, M^3, R * M^3
+};
+
+__host__ __device__ inline int64_t lat_num(const Lat &L, int64_t m, int64_t i1,
+                                           int64_t i2, int64_t i3) {
+  return i1 * m * L.M * L.M + i2 * m * m * L.M + i3 * m * m * m;
+}
+
+__host__ __device__ inline int64_t floor_div(int64_t a, int64_t b) {  // b > 0
+  int64_t q = a / b;
+  return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+__host__ __device__ inline int32_t lat_offset(const Lat &L, int64_t num) {
+  return (int32_t)floor_div(2 * num + L.RM3, 2 * L.RM3);
+}
+
+// (Num mod M^3) / M^3 * 2 as the argument of sincospi.
+__host__ __device__ inline double lat_turns2(const Lat &L, int64_t num) {
+  int64_t r = num % L.M3;
+  if (r < 0) r += L.M3;
+  return 2.0 * (double)r / (double)L.M3;
+}
+
+__device__ inline float2 lat_phasor(const Lat &L, int64_t num) {
+  double s, c;
+  sincospi(lat_turns2(L, num), &s, &c);
+  return make_float2((float)c, (float)s);
+}
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+enum { KTILE = 64 };      // pulses are padded to a multiple of this
+enum { ROWTILE = 128 };   // range rows are padded to a multiple of this
+enum { COLTILE = 128 };   // fine-search columns padded to a multiple of this
+
+struct dsgrft_plan_s {
+  dsgrft_radar radar;
+  dsgrft_config cfg;
+  int device;
+  int M, N, P, n_begin, n_end, rows;
+  int R, h;
+  int K[3], ilo[3];
+  int64_t n_coarse, n_fine;
+  int C;    // fine-search columns per gathered unit: R^min(P, 2)
+  int R3;   // gathered units per coarse cell: R for P = 3, else 1
+  double lam, dr, T, step[3];
+  Lat lat;
+  // padded sizes
+  int Mp, rows_p, Cp, KB, NB, FB;
+  int64_t batch_units, batch_cells;
+  // device buffers owned by the plan
+  float2 *F32;          // [Mp][Cp] fine phasors, complex64
+  uint4 *F16;           // MFMA fragments, 4 planes (re_hi, im_hi, re_lo, im_lo)
+  uint4 *FBF16;         // same in bf16
+  uint4 *F8;            // fp8 e4m3 fragments (K blocks of 64), 4 planes
+  int32_t *u_off;       // [batch_units][Mp] unit range offsets
+  float2 *u_psi;        // [batch_units][Mp] unit de-ramp phasors
+  void *G;              // gathered batch, max 8 bytes per (unit,row,pulse)
+  float *g_scale;       // [batch_units][rows_p] per-row fp8 scales
+  unsigned long long *packed;  // [batch_cells][rows] (power bits, ~fine)
+  void *det_ws;         // detection partials
+  size_t det_ws_bytes;
+  double *adj_ws;       // adjoint scratch
+  size_t adj_ws_bytes;
+  size_t ws_bytes;
+};
+
+// Cell id of the i-th listed cell.
+__device__ inline int64_t cell_id(const int64_t *cells, int64_t base, int64_t i) {
+  return cells ? cells[i] : base + i;
+}
+
+// Coarse centre indices of cell k.
+__host__ __device__ inline void coarse_centre(const int *K, const int *ilo, int R,
+                                              int P, int64_t k, int64_t ic[3]) {
+  int64_t k1 = k % K[0];
+  int64_t k2 = (k / K[0]) % K[1];
+  int64_t k3 = k / ((int64_t)K[0] * K[1]);
+  int64_t kk[3] = {k1, k2, k3};
+  for (int p = 0; p < 3; ++p)
+    ic[p] = (p < P) ? (int64_t)ilo[p] + kk[p] * R + R / 2 : 0;
+}
+
+// Fine offsets of flat fine index f.
+__host__ __device__ inline void fine_offsets(int R, int P, int64_t f, int64_t fo[3]) {
+  int64_t u = f;
+  for (int p = 0; p < 3; ++p) {
+    fo[p] = (p < P) ? (u % R) - R / 2 : 0;
+    u /= R;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers (implemented in the .hip files)
+// ---------------------------------------------------------------------------
+#define DS_TRY(expr)                                     \
+  do {                                                   \
+    if ((expr) != hipSuccess) return DSGRFT_E_DEVICE;    \
+  } while (0)
+
+hipError_t launch_fine_tables(dsgrft_plan p, hipStream_t s);
+hipError_t launch_unit_tables(dsgrft_plan p, const int64_t *cells,
+                              int64_t cc_base, int64_t unit0, int64_t nunits,
+                              hipStream_t s);
+hipError_t launch_coarse_tables(dsgrft_plan p, int64_t cc_begin, int64_t n,
+                                int stride, int32_t *off, float2 *psi,
+                                hipStream_t s);
+size_t detect_ws_bytes(int64_t max_entries);
+hipError_t launch_gather_f32(dsgrft_plan p, const float2 *echo, int64_t nunits,
+                             hipStream_t s);
+hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
+                            const float2 *echo, int64_t nunits, hipStream_t s);
+hipError_t launch_mgift_out(dsgrft_plan p, const float2 *echo, int64_t nunits,
+                            float2 *out, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *ptr, int64_t n, hipStream_t s);
+hipError_t launch_fine_f32(dsgrft_plan p, int64_t nunits, int64_t unit0,
+                           float *full, int64_t full_cell0, hipStream_t s);
+hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
+                            int64_t nunits, int64_t unit0, float *full,
+                            hipStream_t s);
+hipError_t launch_unpack(dsgrft_plan p, int64_t ncells, float *pmax,
+                         int32_t *argf, hipStream_t s);
+hipError_t launch_grft(dsgrft_plan p, const float2 *echo, int64_t cc_begin,
+                       int64_t n, float *full, hipStream_t s);
+hipError_t launch_noise_power(dsgrft_plan p, const float2 *echo, double *out,
+                              hipStream_t s);
+hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
+                         const int64_t *cells, int64_t cc_begin, int64_t n,
+                         double gamma2, dsgrft_peak *peaks, int32_t cap,
+                         int32_t *count, dsgrft_peak *best, hipStream_t s);
+hipError_t launch_adjoint_forward(dsgrft_plan p, const float2 *echo,
+                                  const double *theta, int B, double *J,
+                                  double *saved, hipStream_t s);
+hipError_t launch_adjoint_backward(dsgrft_plan p, const float2 *echo,
+                                   const double *theta, int B,
+                                   const double *saved, const double *gJ,
+                                   double *grad_theta, float2 *grad_echo,
+                                   hipStream_t s);
+hipError_t launch_refine(dsgrft_plan p, const float2 *echo, double *theta, int B,
+                         int iters, double *J, hipStream_t s);

@@ -1,0 +1,197 @@
+"""Python face of the DS-GRFT library: one `Plan` per radar/lattice setup.
+
+Methods take and return torch tensors on the plan's GPU and pass their
+device pointers and the current HIP stream straight to the C ABI; torch is
+used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FORMS, PEAK_DTYPE, check
+
+CFG_FIELDS = ("M", "N", "order")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _echo(echo: torch.Tensor) -> torch.Tensor:
+    if echo.dtype != torch.complex64 or not echo.is_cuda or not echo.is_contiguous():
+        raise ValueError("echo must be a contiguous complex64 CUDA tensor [M][N]")
+    return echo
+
+
+class Plan:
+    """Dual-scale lattice, fine tables and workspace for one search setup.
+
+    fc, fs, prf: carrier [Hz], range sampling rate [Hz], PRF [Hz];
+    axes: [(vmin, vmax), (amin, amax), (jmin, jmax)][:order];
+    rows: optional (n_begin, n_end) range rows of interest.
+    """
+
+    def __init__(self, fc, fs, prf, M, N, order, axes, rows=None, c=3.0e8,
+                 kappa=1.0, batch=0):
+        L = _lib.lib()
+        radar = _lib.Radar(fc, fs, prf, c, kappa)
+        cfg = _lib.Config()
+        cfg.M, cfg.N, cfg.order = M, N, order
+        cfg.n_begin, cfg.n_end = (0, 0) if rows is None else rows
+        for p, ax in enumerate(axes):
+            cfg.axis[p].min, cfg.axis[p].max = float(ax[0]), float(ax[1])
+        cfg.batch = batch
+        h = C.c_void_p()
+        check("dsgrft_plan_create", L.dsgrft_plan_create(C.byref(radar), C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._L = L
+        info = _lib.PlanInfo()
+        check("dsgrft_plan_get_info", L.dsgrft_plan_get_info(h, C.byref(info)))
+        self.M, self.N, self.order = M, N, order
+        self.R = info.R
+        self.K = tuple(info.K)
+        self.i_lo = tuple(info.i_lo)
+        self.rows = info.rows
+        self.n_begin = cfg.n_begin
+        self.n_coarse = info.n_coarse
+        self.n_fine = info.n_fine
+        self.lam, self.dr, self.T = info.lambda_, info.dr, info.T
+        self.step = tuple(info.step)
+        self.workspace_bytes = info.workspace_bytes
+        self.prf = prf
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.dsgrft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- stage a0 / a1+a2 readback --------------------------------------
+    def coarse_tables(self, cc_begin=0, n=None):
+        n = self.n_coarse - cc_begin if n is None else n
+        off = torch.empty((n, self.M), dtype=torch.int32, device="cuda")
+        psi = torch.empty((n, self.M), dtype=torch.complex64, device="cuda")
+        check("dsgrft_coarse_tables", self._L.dsgrft_coarse_tables(
+            self._h, cc_begin, n, _ptr(off), _ptr(psi), _stream()))
+        return off, psi
+
+    def mgift(self, echo, cc_begin=0, n=None):
+        echo = _echo(echo)
+        n = self.n_coarse - cc_begin if n is None else n
+        out = torch.empty((n, self.M, self.rows), dtype=torch.complex64, device="cuda")
+        check("dsgrft_mgift", self._L.dsgrft_mgift(
+            self._h, _ptr(echo), cc_begin, n, _ptr(out), _stream()))
+        return out
+
+    # ---- search -----------------------------------------------------------
+    def search(self, echo, form="f16", split=1, cells=None, cc_begin=0, n=None,
+               out=None):
+        """Reduced DS-GRFT map: (pmax [n, rows] float32, argf [n, rows] int32)."""
+        echo = _echo(echo)
+        if cells is not None:
+            cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
+            n = cells.numel()
+        else:
+            n = self.n_coarse - cc_begin if n is None else n
+        if out is None:
+            pmax = torch.empty((n, self.rows), dtype=torch.float32, device="cuda")
+            argf = torch.empty((n, self.rows), dtype=torch.int32, device="cuda")
+        else:
+            pmax, argf = out
+        check("dsgrft_search", self._L.dsgrft_search(
+            self._h, FORMS[form], split, _ptr(echo), _ptr(cells), cc_begin, n,
+            _ptr(pmax), _ptr(argf), _stream()))
+        return pmax, argf
+
+    def search_full(self, echo, form="f32", split=1, cc_begin=0, n=None):
+        echo = _echo(echo)
+        n = self.n_coarse - cc_begin if n is None else n
+        pw = torch.empty((n, self.rows, self.n_fine), dtype=torch.float32, device="cuda")
+        check("dsgrft_search_full", self._L.dsgrft_search_full(
+            self._h, FORMS[form], split, _ptr(echo), cc_begin, n, _ptr(pw), _stream()))
+        return pw
+
+    def grft(self, echo, cc_begin=0, n=None, full=False):
+        echo = _echo(echo)
+        n = self.n_coarse - cc_begin if n is None else n
+        pmax = torch.empty((n, self.rows), dtype=torch.float32, device="cuda")
+        argf = torch.empty((n, self.rows), dtype=torch.int32, device="cuda")
+        pw = (torch.empty((n, self.rows, self.n_fine), dtype=torch.float32, device="cuda")
+              if full else None)
+        check("dsgrft_grft", self._L.dsgrft_grft(
+            self._h, _ptr(echo), cc_begin, n, _ptr(pmax), _ptr(argf), _ptr(pw), _stream()))
+        return (pmax, argf, pw) if full else (pmax, argf)
+
+    # ---- detection ----------------------------------------------------------
+    def noise_power(self, echo) -> float:
+        echo = _echo(echo)
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        check("dsgrft_noise_power", self._L.dsgrft_noise_power(
+            self._h, _ptr(echo), _ptr(out), _stream()))
+        return float(out.item())
+
+    def detect(self, pmax, argf, gamma2, cap=1024, cells=None, cc_begin=0):
+        """Threshold test on a reduced map.  Returns (peaks structured numpy
+        array [min(count, cap)], count, best peak)."""
+        n = pmax.shape[0]
+        if cells is not None:
+            cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
+        peaks = torch.empty((max(cap, 1), PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+        best = torch.empty((1, PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        check("dsgrft_detect", self._L.dsgrft_detect(
+            self._h, _ptr(pmax), _ptr(argf), _ptr(cells), cc_begin, n, float(gamma2),
+            _ptr(peaks), cap, _ptr(count), _ptr(best), _stream()))
+        cnt = int(count.item())
+        pk = peaks[:min(cnt, cap)].cpu().numpy().view(PEAK_DTYPE).reshape(-1)
+        bp = best.cpu().numpy().view(PEAK_DTYPE).reshape(-1)[0]
+        return pk, cnt, bp
+
+    def threshold(self, sigma2, pfa):
+        """gamma^2 = -M sigma^2 ln P_FA on |Y|^2."""
+        return -self.M * float(sigma2) * float(np.log(pfa))
+
+    # ---- adjoint --------------------------------------------------------------
+    def adjoint_forward(self, echo, theta):
+        echo = _echo(echo)
+        theta = theta.to(device="cuda", dtype=torch.float64).contiguous()
+        B = theta.shape[0]
+        J = torch.empty(B, dtype=torch.float64, device="cuda")
+        saved = torch.empty((B, 8), dtype=torch.float64, device="cuda")
+        check("dsgrft_adjoint_forward", self._L.dsgrft_adjoint_forward(
+            self._h, _ptr(echo), _ptr(theta), B, _ptr(J), _ptr(saved), _stream()))
+        return J, saved
+
+    def adjoint_backward(self, echo, theta, saved, gJ, want_theta=True, want_echo=True):
+        echo = _echo(echo)
+        theta = theta.to(device="cuda", dtype=torch.float64).contiguous()
+        gJ = gJ.to(device="cuda", dtype=torch.float64).contiguous()
+        B = theta.shape[0]
+        gt = torch.empty((B, 3), dtype=torch.float64, device="cuda") if want_theta else None
+        ge = torch.empty((self.M, self.N), dtype=torch.complex64, device="cuda") if want_echo else None
+        check("dsgrft_adjoint_backward", self._L.dsgrft_adjoint_backward(
+            self._h, _ptr(echo), _ptr(theta), B, _ptr(saved), _ptr(gJ), _ptr(gt),
+            _ptr(ge), _stream()))
+        return gt, ge
+
+    def refine(self, echo, theta, iters=30):
+        echo = _echo(echo)
+        th = theta.to(device="cuda", dtype=torch.float64).clone().contiguous()
+        B = th.shape[0]
+        J = torch.empty(B, dtype=torch.float64, device="cuda")
+        check("dsgrft_refine", self._L.dsgrft_refine(
+            self._h, _ptr(echo), _ptr(th), B, iters, _ptr(J), _stream()))
+        return th, J

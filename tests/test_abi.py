@@ -1,0 +1,82 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/dsgrft.h, and rejects invalid arguments before touching
+the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2403_06788_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dsgrft.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH),
+                                reason="libdsgrft.so not built")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsgrft_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_surface():
+    assert declared_functions() == sorted(_lib.exported_symbols())
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = _lib.lib()
+    assert L.dsgrft_status_string(0) == b"ok"
+    assert L.dsgrft_status_string(4) == b"unsupported request"
+    assert L.dsgrft_status_string(99) == b"unknown status"
+
+
+def _create(fc=1e9, fs=1e7, prf=500.0, M=64, N=256, order=1, axes=((-150, 150),),
+            kappa=1.0, rows=(0, 0), batch=0, c=3e8):
+    L = _lib.lib()
+    r = _lib.Radar(fc, fs, prf, c, kappa)
+    cfg = _lib.Config()
+    cfg.M, cfg.N, cfg.order = M, N, order
+    cfg.n_begin, cfg.n_end = rows
+    for p, ax in enumerate(axes):
+        cfg.axis[p].min, cfg.axis[p].max = ax
+    cfg.batch = batch
+    h = C.c_void_p()
+    return L.dsgrft_plan_create(C.byref(r), C.byref(cfg), C.byref(h))
+
+
+@pytest.mark.parametrize("kw", [
+    dict(M=0), dict(N=0), dict(order=0), dict(order=4),
+    dict(fs=3e7),                       # f_c / f_s not an integer
+    dict(fc=-1.0), dict(prf=0.0), dict(c=float("nan")),
+    dict(axes=((150, -150),)),          # min > max
+    dict(rows=(10, 5)), dict(rows=(0, 300)), dict(rows=(-1, 10)),
+    dict(batch=-1),
+    dict(M=2048, order=3, axes=((-1e12, 1e12), (-1, 1), (-1, 1))),  # numerator overflow
+])
+def test_plan_create_rejects_invalid(kw):
+    assert _create(**kw) == 1
+
+
+def test_plan_create_kappa_unsupported():
+    assert _create(kappa=0.995) == 4
+
+
+def test_null_pointers_rejected():
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.dsgrft_plan_create(None, None, C.byref(h)) == 1
+    assert L.dsgrft_search(None, 1, 1, None, None, 0, 1, None, None, None) == 1
+    assert L.dsgrft_detect(None, None, None, None, 0, 1, 1.0, None, 0, None, None, None) == 1
+    assert L.dsgrft_adjoint_forward(None, None, None, 1, None, None, None) == 1
+    info = _lib.PlanInfo()
+    assert L.dsgrft_plan_get_info(None, C.byref(info)) == 1
+    L.dsgrft_plan_destroy(None)  # accepted
