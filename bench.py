@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""DS-GRFT throughput benchmark on one MI355X.
+
+Workload: the M = 1024 search (N = 4096 range bins, P = 2, v in +-600 m/s,
+a in +-50 m/s^2; 2460 coarse cells x 10^4 fine cells x 4096 rows = 1.008e11
+cells, 1.03e14 cells*pulses) on a seeded synthetic echo with 8 targets at
+-20 dB per-pulse SNR.  One step = the whole DS-GRFT hot path over the echo
+(coarse tables, gather + de-ramp, fine search with fused |.|^2/argmax,
+LRT detection with peak parameters), echo already resident in HBM.
+
+Prints one JSON line (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DS-GRFT cells·pulses/s (M=1024); MFMA vs FP32 speedup at rel err≤1e-3"
+PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
+HBM_GBPS = 8000.0
+FINE_SRC = os.path.join(ROOT, "paper_2403_06788_amd", "csrc", "fine_mfma.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fine_mfma_f16_m1024_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(FINE_SRC, "rb").read()).hexdigest()[:16]
+
+
+def recorded_traffic(form, split):
+    """Per-launch HBM traffic of the fine kernel from the committed rocprofv3
+    counter summary, or None if absent or taken on another kernel version."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_hash() or d.get("form") != f"{form}x{split}":
+        return None
+    return d.get("bytes_per_launch")
+
+
+def oracle_rows(echo, grid, cells, rows):
+    """Oracle reduced values for sampled (cell, rows): list of (P_row [R^P])."""
+    import numpy as np
+    from oracle import transforms as OT
+    out = {}
+    for k in cells:
+        y = OT.dsgrft_cell(echo, grid, int(k), rows=rows)
+        out[int(k)] = np.abs(y) ** 2
+    return out
+
+
+def sampled_error(pm, af, ref, rows, tol):
+    """max |dP|/P_ref_max over sampled rows, and argmax agreement (near-tie
+    rule: exact where the oracle's top-2 gap exceeds 2 tol * scale)."""
+    import numpy as np
+    scale = max(float(v.max()) for v in ref.values())
+    err, bad, clear = 0.0, 0, 0
+    for k, P in ref.items():
+        pm_o, af_o = P.max(-1), P.argmax(-1)
+        srt = np.sort(P, -1)
+        gap = srt[:, -1] - srt[:, -2]
+        for i, r in enumerate(rows):
+            e = abs(float(pm[k, r]) - pm_o[i]) / scale
+            err = max(err, e)
+            if gap[i] > 2 * tol * scale:
+                clear += 1
+                bad += int(af[k, r] != af_o[i])
+            elif P[i, af[k, r]] < pm_o[i] - 2 * tol * scale:
+                bad += 1
+    return err, bad, clear, scale
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--form", default="f16")
+    ap.add_argument("--split", type=int, default=1)
+    ap.add_argument("--f32-cells", type=int, default=48)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short run for rocprofv3 counter passes")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the search "
+                          "shards over coarse cells but multi-GPU runs are "
+                          "not part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_06788_amd.plan import Plan
+
+    case = synth.config_case(3)
+    c = synth.CONFIGS[3]
+    r = c["radar"]
+    echo_np = case["echo"]
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"])
+    echo = torch.from_numpy(echo_np).cuda()
+    cells = plan.n_coarse
+    cp_total = float(cells) * plan.rows * plan.n_fine * plan.M
+    gamma2 = plan.threshold(1.0, 1e-9)   # sigma^2 = 1 (synthetic), P_FA = 1e-9
+    pm = torch.empty((cells, plan.rows), dtype=torch.float32, device="cuda")
+    af = torch.empty((cells, plan.rows), dtype=torch.int32, device="cuda")
+
+    def step(form, split, n=cells):
+        plan.search(echo, form, split, n=n, out=(pm[:n], af[:n]))
+        return plan.detect(pm[:n], af[:n], gamma2, cap=4096) if n == cells else None
+
+    if args.profile_pass:
+        # calibration copy of known size, then one search of 16 cells
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        plan.search(echo, args.form, args.split, n=16, out=(pm[:16], af[:16]))
+        torch.cuda.synchronize()
+        log(f"profile pass done: copy 1 GiB + {args.form}x{args.split} on 16 cells")
+        return
+
+    log(f"plan: {cells} coarse cells x {plan.n_fine} fine x {plan.rows} rows, "
+        f"M={plan.M}; workspace {plan.workspace_bytes / 2**20:.0f} MiB")
+    for _ in range(args.warmup):
+        step(args.form, args.split)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+    plan.profile_begin(4096)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.form, args.split)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = plan.profile_end()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = cp_total / (ms * 1e-3)
+    log(f"timed {args.steps} steps: {ms:.1f} ms/step, {value:.3e} cells*pulses/s")
+    pm_main, af_main = pm.cpu().numpy(), af.cpu().numpy()
+    peaks, count, best = plan.detect(pm, af, gamma2, cap=4096)
+
+    fine_avg_s = prof["fine_ms"] / max(prof["fine_launches"], 1) * 1e-3
+    fine_flops_launch = prof["fine_flops"] / max(prof["fine_launches"], 1)
+    achieved = fine_flops_launch / fine_avg_s / 1e12
+    peak = PEAK_TFLOPS[args.form]
+    gather_avg_s = prof["gather_ms"] / max(prof["gather_launches"], 1) * 1e-3
+    gather_bytes = prof["gather_bytes"] / max(prof["gather_launches"], 1)
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": recorded_traffic(args.form, args.split),
+                "kernel": f"k_fine_mfma<{args.form}, split {args.split}>",
+                "avg_launch_ms": round(fine_avg_s * 1e3, 4),
+                "flops_per_launch": fine_flops_launch,
+                "launches": prof["fine_launches"]}
+    gather = {"bound": "hbm", "achieved": round(gather_bytes / gather_avg_s / 1e9, 1),
+              "peak": HBM_GBPS, "unit": "GB/s",
+              "frac": round(gather_bytes / gather_avg_s / 1e9 / HBM_GBPS, 4),
+              "avg_launch_ms": round(gather_avg_s * 1e3, 4),
+              "bytes_per_launch": gather_bytes}
+    log(f"fine kernel: {achieved:.1f} TFLOP/s ({achieved / peak:.1%} of {peak}); "
+        f"gather {gather['achieved']:.0f} GB/s")
+
+    # ---- accuracy on sampled rows vs the FP64 oracle ----------------------
+    from oracle.grid import Axis, Radar, make_grid
+    grid = make_grid(Radar(r.fc, r.fs, r.prf), c["M"], c["N"], c["order"],
+                     [Axis(*a) for a in c["axes"]])
+    rng = np.random.default_rng(2024)
+    bk, brow = int(best["coarse"]), int(best["row"])
+    s_cells = sorted(set([bk] + [int(x) for x in rng.choice(cells, 5, replace=False)]))
+    s_rows = sorted(set([brow] + [int(x) for x in rng.choice(plan.rows, 40, replace=False)]))
+    t = time.perf_counter()
+    ref = oracle_rows(echo_np, grid, s_cells, s_rows)
+    log(f"oracle rows: {len(s_cells)} cells x {len(s_rows)} rows in {time.perf_counter() - t:.1f} s")
+    forms = {}
+    err, bad, clear, scale = sampled_error(pm_main, af_main, ref, s_rows, 1e-3)
+    forms[f"{args.form}x{args.split}"] = {"cells_pulses_per_s": value, "ms": round(ms, 2),
+                                         "rel_err": err, "argmax_bad": bad,
+                                         "argmax_checked": clear}
+    # ---- other forms: one warm step each ----------------------------------
+    if not args.no_sweep:
+        for form, split in (("bf16", 3), ("bf16", 1), ("f16", 3)):
+            if (form, split) == (args.form, args.split):
+                continue
+            step(form, split, n=16)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            step(form, split)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            e, b, cl, _ = sampled_error(pm.cpu().numpy(), af.cpu().numpy(), ref, s_rows, 1e-3)
+            forms[f"{form}x{split}"] = {"cells_pulses_per_s": cp_total / dt,
+                                        "ms": round(dt * 1e3, 2), "rel_err": e,
+                                        "argmax_bad": b, "argmax_checked": cl}
+            log(f"{form}x{split}: {dt * 1e3:.1f} ms, rel err {e:.2e}")
+    # ---- plain FP32 form on a sample of coarse cells ------------------------
+    n32 = min(args.f32_cells, cells)
+    step("f32", 1, n=16)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    step("f32", 1, n=n32)
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t
+    cp32 = float(n32) * plan.rows * plan.n_fine * plan.M
+    f32_rate = cp32 / dt32
+    pm32, af32 = pm[:n32].cpu().numpy(), af[:n32].cpu().numpy()
+    ref32 = {k: v for k, v in ref.items() if k < n32}
+    e32 = sampled_error(pm32, af32, ref32, s_rows, 1e-5)[0] if ref32 else None
+    forms["f32x1"] = {"cells_pulses_per_s": f32_rate, "sample_cells": n32,
+                      "ms_sample": round(dt32 * 1e3, 2), "rel_err": e32}
+    log(f"f32 plain: {f32_rate:.3e} cells*pulses/s on {n32} cells")
+    ok_forms = {k: v for k, v in forms.items()
+                if k != "f32x1" and v["rel_err"] <= 1e-3 and v["argmax_bad"] == 0}
+
+    # ---- CPU baseline: the oracle on a bounded sample ------------------------
+    cpu = None
+    if not args.no_cpu:
+        from oracle import detect as OD
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        except Exception:
+            threads = os.cpu_count()
+        t = time.perf_counter()
+        done = 0
+        while done < 4 and (done == 0 or time.perf_counter() - t < 10.0):
+            OD.dsgrft_reduced(echo_np, grid, cells=[done])
+            done += 1
+        dtc = time.perf_counter() - t
+        cpu = {"value": done * plan.rows * plan.n_fine * plan.M / dtc,
+               "unit": "cells·pulses/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"{done} coarse cells x {plan.rows} rows x {plan.n_fine} fine "
+                         f"x {plan.M} pulses in {dtc:.1f} s (FP64 numpy, BLAS threads "
+                         f"{threads}, host cpu_count {os.cpu_count()})"}
+        log(f"cpu oracle: {cpu['value']:.3e} cells*pulses/s")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cells·pulses/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.form, "data": "synthetic",
+        "config": {"workload": "DS-GRFT search, M=1024 pulses, N=4096 range bins, "
+                               "P=2 (v +-600 m/s, a +-50 m/s^2), 2460 coarse x 10^4 fine "
+                               "cells, 8 targets at -20 dB, fc=1 GHz, fs=10 MHz, PRF=500 Hz",
+                   "form": f"{args.form} MFMA, split {args.split}, FP32 accumulation",
+                   "cells": cells * plan.rows * plan.n_fine, "pulses": plan.M},
+        "roofline": roofline,
+        "gather_roofline": gather,
+        "cpu_baseline": cpu,
+        "speedup_vs_f32": round(value / f32_rate, 2),
+        "rel_err": err,
+        "detections": int(count),
+        "forms": forms,
+        "forms_within_1e-3": sorted(ok_forms),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

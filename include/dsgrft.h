@@ -229,6 +229,27 @@ dsgrft_status dsgrft_refine(dsgrft_plan plan, const void *d_echo,
                             double *d_theta, int32_t B, int32_t iters,
                             double *d_J, void *stream);
 
+/* Kernel timing for measurement.  Between dsgrft_profile_begin and
+ * dsgrft_profile_end the plan records a HIP event pair (on the caller's
+ * stream) around each launch of the gather kernel (stages a1 + a2) and of
+ * the fine-search kernel (stages a3 + a4) issued by dsgrft_search, for at
+ * most `capacity` launches of each; later launches are not timed.  begin
+ * creates the events (it is not an execution call) and resets the counters;
+ * end synchronises the device, sums the event durations and destroys the
+ * events.  Algorithmic work per launch: gather bytes = units x rows x M x
+ * (8 read + bytes per gathered sample written); fine flops = 8 per
+ * cell-pulse (one complex multiply-add), independent of the split. */
+typedef struct {
+  int64_t gather_launches, fine_launches;  /* timed launches               */
+  double gather_ms, fine_ms;               /* summed durations            */
+  double gather_bytes;                     /* algorithmic bytes, timed    */
+  double fine_flops;                       /* algorithmic flops, timed    */
+  double fine_cell_pulses;                 /* cells x pulses, timed       */
+} dsgrft_profile;
+
+dsgrft_status dsgrft_profile_begin(dsgrft_plan plan, int32_t capacity);
+dsgrft_status dsgrft_profile_end(dsgrft_plan plan, dsgrft_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,6 +50,13 @@ class PlanInfo(C.Structure):
                 ("step", C.c_double * 3), ("workspace_bytes", C.c_size_t)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("gather_launches", C.c_int64), ("fine_launches", C.c_int64),
+                ("gather_ms", C.c_double), ("fine_ms", C.c_double),
+                ("gather_bytes", C.c_double), ("fine_flops", C.c_double),
+                ("fine_cell_pulses", C.c_double)]
+
+
 PEAK_DTYPE = np.dtype({
     "names": ["coarse", "row", "fine", "power", "pad", "r0", "v", "a", "j"],
     "formats": [np.int64, np.int32, np.int32, np.float32, np.float32,
@@ -82,6 +89,8 @@ def lib():
         "dsgrft_adjoint_forward": [vp, vp, vp, i32, vp, vp, vp],
         "dsgrft_adjoint_backward": [vp, vp, vp, i32, vp, vp, vp, vp, vp],
         "dsgrft_refine": [vp, vp, vp, i32, i32, vp, vp],
+        "dsgrft_profile_begin": [vp, i32],
+        "dsgrft_profile_end": [vp, C.POINTER(Profile)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -106,4 +115,5 @@ def exported_symbols():
             "dsgrft_status_string", "dsgrft_coarse_tables", "dsgrft_mgift",
             "dsgrft_search", "dsgrft_search_full", "dsgrft_grft",
             "dsgrft_noise_power", "dsgrft_detect", "dsgrft_adjoint_forward",
-            "dsgrft_adjoint_backward", "dsgrft_refine"]
+            "dsgrft_adjoint_backward", "dsgrft_refine",
+            "dsgrft_profile_begin", "dsgrft_profile_end"]

@@ -85,12 +85,30 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
     for (int64_t u0 = 0; u0 < nut; u0 += Bu) {
       const int64_t nu = (nut - u0) < Bu ? (nut - u0) : Bu;
       DS_TRY(launch_unit_tables(p, cl, cc_begin + c0, u0, nu, s));
-      if (form == DSGRFT_FORM_F32) {
+      auto &pr = p->prof;
+      const bool tg = pr.ng < pr.cap, tf = pr.nf < pr.cap;
+      const double samples = (double)nu * p->rows * p->M;
+      const double bg = form == DSGRFT_FORM_F32 ? 8.0 : (split == 1 ? 4.0 : 8.0);
+      if (tg) DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng], s));
+      if (form == DSGRFT_FORM_F32)
         DS_TRY(launch_gather_f32(p, echo, nu, s));
-        DS_TRY(launch_fine_f32(p, nu, u0, fl, 0, s));
-      } else {
+      else
         DS_TRY(launch_gather_lp(p, form, split, echo, nu, s));
+      if (tg) {
+        DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng + 1], s));
+        pr.ng++;
+        pr.gbytes += samples * (8.0 + bg);
+      }
+      if (tf) DS_TRY(hipEventRecord(pr.ev_f[2 * pr.nf], s));
+      if (form == DSGRFT_FORM_F32)
+        DS_TRY(launch_fine_f32(p, nu, u0, fl, 0, s));
+      else
         DS_TRY(launch_fine_mfma(p, form, split, nu, u0, fl, s));
+      if (tf) {
+        DS_TRY(hipEventRecord(pr.ev_f[2 * pr.nf + 1], s));
+        pr.nf++;
+        pr.fcp += samples * p->C;
+        pr.fflops += 8.0 * samples * p->C;
       }
     }
     if (pmax && argf)
@@ -262,9 +280,12 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   return DSGRFT_OK;
 }
 
+static void prof_free(dsgrft_plan p);
+
 void dsgrft_plan_destroy(dsgrft_plan plan) {
   if (!plan) return;
   (void)hipDeviceSynchronize();
+  prof_free(plan);
   release(plan);
 }
 
@@ -417,6 +438,76 @@ dsgrft_status dsgrft_refine(dsgrft_plan p, const void *d_echo, double *d_theta,
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   DS_TRY(launch_refine(p, (const float2 *)d_echo, d_theta, B, iters, d_J,
                        (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
+static void prof_free(dsgrft_plan p) {
+  auto &pr = p->prof;
+  for (int i = 0; i < 2 * pr.cap; ++i) {
+    if (pr.ev_g && pr.ev_g[i]) (void)hipEventDestroy(pr.ev_g[i]);
+    if (pr.ev_f && pr.ev_f[i]) (void)hipEventDestroy(pr.ev_f[i]);
+  }
+  std::free(pr.ev_g);
+  std::free(pr.ev_f);
+  pr = dsgrft_plan_s::Prof();
+}
+
+dsgrft_status dsgrft_profile_begin(dsgrft_plan p, int32_t capacity) {
+  if (!p || capacity < 1 || capacity > (1 << 20)) return DSGRFT_E_INVALID;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  prof_free(p);
+  auto &pr = p->prof;
+  pr.ev_g = (hipEvent_t *)std::calloc(2 * (size_t)capacity, sizeof(hipEvent_t));
+  pr.ev_f = (hipEvent_t *)std::calloc(2 * (size_t)capacity, sizeof(hipEvent_t));
+  if (!pr.ev_g || !pr.ev_f) {
+    prof_free(p);
+    return DSGRFT_E_NOMEM;
+  }
+  pr.cap = capacity;
+  for (int i = 0; i < 2 * capacity; ++i) {
+    if (hipEventCreate(&pr.ev_g[i]) != hipSuccess ||
+        hipEventCreate(&pr.ev_f[i]) != hipSuccess) {
+      prof_free(p);
+      return DSGRFT_E_DEVICE;
+    }
+  }
+  return DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_profile_end(dsgrft_plan p, dsgrft_profile *out) {
+  if (!p || !out) return DSGRFT_E_INVALID;
+  auto &pr = p->prof;
+  std::memset(out, 0, sizeof(*out));
+  if (pr.cap == 0) return DSGRFT_E_INVALID;
+  if (hipDeviceSynchronize() != hipSuccess) {
+    prof_free(p);
+    return DSGRFT_E_DEVICE;
+  }
+  double gms = 0.0, fms = 0.0;
+  for (int i = 0; i < pr.ng; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.ev_g[2 * i], pr.ev_g[2 * i + 1]) != hipSuccess) {
+      prof_free(p);
+      return DSGRFT_E_DEVICE;
+    }
+    gms += ms;
+  }
+  for (int i = 0; i < pr.nf; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.ev_f[2 * i], pr.ev_f[2 * i + 1]) != hipSuccess) {
+      prof_free(p);
+      return DSGRFT_E_DEVICE;
+    }
+    fms += ms;
+  }
+  out->gather_launches = pr.ng;
+  out->fine_launches = pr.nf;
+  out->gather_ms = gms;
+  out->fine_ms = fms;
+  out->gather_bytes = pr.gbytes;
+  out->fine_flops = pr.fflops;
+  out->fine_cell_pulses = pr.fcp;
+  prof_free(p);
   return DSGRFT_OK;
 }
 

@@ -50,7 +50,7 @@ __device__ inline float2 lat_phasor(const Lat &L, int64_t num) {
 // Plan
 // ---------------------------------------------------------------------------
 enum { KTILE = 64 };      // pulses are padded to a multiple of this
-enum { ROWTILE = 128 };   // range rows are padded to a multiple of this
+enum { ROWTILE = 256 };   // range rows are padded to a multiple of this
 enum { COLTILE = 128 };   // fine-search columns padded to a multiple of this
 
 struct dsgrft_plan_s {
@@ -83,6 +83,13 @@ struct dsgrft_plan_s {
   double *adj_ws;       // adjoint scratch
   size_t adj_ws_bytes;
   size_t ws_bytes;
+  // measurement hook (dsgrft_profile_begin / _end)
+  struct Prof {
+    int cap = 0;
+    int ng = 0, nf = 0;
+    hipEvent_t *ev_g = nullptr, *ev_f = nullptr;  // [2 * cap] each
+    double gbytes = 0.0, fflops = 0.0, fcp = 0.0;
+  } prof;
 };
 
 // Cell id of the i-th listed cell.

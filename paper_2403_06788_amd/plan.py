@@ -164,6 +164,15 @@ class Plan:
         """gamma^2 = -M sigma^2 ln P_FA on |Y|^2."""
         return -self.M * float(sigma2) * float(np.log(pfa))
 
+    # ---- measurement -----------------------------------------------------
+    def profile_begin(self, capacity=4096):
+        check("dsgrft_profile_begin", self._L.dsgrft_profile_begin(self._h, capacity))
+
+    def profile_end(self) -> dict:
+        pr = _lib.Profile()
+        check("dsgrft_profile_end", self._L.dsgrft_profile_end(self._h, C.byref(pr)))
+        return {k: getattr(pr, k) for k, _ in pr._fields_}
+
     # ---- adjoint --------------------------------------------------------------
     def adjoint_forward(self, echo, theta):
         echo = _echo(echo)
