@@ -93,6 +93,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for rocprofv3 counter passes")
+    ap.add_argument("--workload", type=int, default=3, choices=(3, 4, 5),
+                    help="3: the M=1024 search (default, headline metric); "
+                         "4: adjoint at M=512; 5: third-order search at M=2048 "
+                         "on a 64-coarse-cell subset")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -107,6 +111,10 @@ def main():
     import synth
     from paper_2403_06788_amd.plan import Plan
 
+    if args.workload == 4:
+        return bench_adjoint(args)
+    if args.workload == 5:
+        return bench_jerk(args)
     case = synth.config_case(3)
     c = synth.CONFIGS[3]
     r = c["radar"]
@@ -181,7 +189,7 @@ def main():
                      [Axis(*a) for a in c["axes"]])
     rng = np.random.default_rng(2024)
     bk, brow = int(best["coarse"]), int(best["row"])
-    s_cells = sorted(set([bk] + [int(x) for x in rng.choice(cells, 5, replace=False)]))
+    s_cells = sorted(set([bk, 0, 1] + [int(x) for x in rng.choice(cells, 5, replace=False)]))
     s_rows = sorted(set([brow] + [int(x) for x in rng.choice(plan.rows, 40, replace=False)]))
     t = time.perf_counter()
     ref = oracle_rows(echo_np, grid, s_cells, s_rows)
@@ -267,6 +275,163 @@ def main():
         "forms": forms,
         "forms_within_1e-3": sorted(ok_forms),
     }
+    print(json.dumps(out), flush=True)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def bench_adjoint(args):
+    """M=512 adjoint: forward + backward over 4096 candidates, gradient checks
+    and off-grid refinement of the target candidates."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_06788_amd.plan import Plan
+    case = synth.config_case(4)
+    c = synth.CONFIGS[4]
+    r = c["radar"]
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"])
+    echo = torch.from_numpy(case["echo"]).cuda()
+    rng = np.random.Generator(np.random.PCG64(1004))
+    th = synth.adjoint_candidates(rng, r, c["M"], c["N"], case["targets"], c["v"], c["a"])
+    theta = torch.from_numpy(th).cuda()
+    gJ = torch.ones(len(th), dtype=torch.float64, device="cuda")
+
+    def step():
+        J, saved = plan.adjoint_forward(echo, theta)
+        return plan.adjoint_backward(echo, theta, saved, gJ)
+    for _ in range(args.warmup):
+        step()
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gt, ge = step()
+    _sync()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # device central differences, candidates away from coarse-cell edges
+    J, _ = plan.adjoint_forward(echo, theta)
+    gt = gt.cpu().numpy()
+    hs = np.array([1e-4 * plan.dr, 1e-4 * plan.step[0], 1e-4 * plan.step[1]])
+    inside = np.ones(len(th), dtype=bool)
+    for p in (0, 1):
+        u = th[:, p + 1] / plan.step[p] - plan.i_lo[p] + 0.5
+        fr = (u / plan.R) % 1.0
+        inside &= (fr > 0.01) & (fr < 0.99)
+    idx = np.nonzero(inside)[0]
+    fd_err = []
+    for q in range(3):
+        e = np.zeros(3)
+        e[q] = hs[q]
+        Jp, _ = plan.adjoint_forward(echo, torch.from_numpy(th[idx] + e))
+        Jm, _ = plan.adjoint_forward(echo, torch.from_numpy(th[idx] - e))
+        fd = (Jp.cpu().numpy() - Jm.cpu().numpy()) / (2 * hs[q])
+        fd_err.append(float(np.abs(fd - gt[idx, q]).max() / np.abs(gt[idx, q]).max()))
+    # oracle gradient on a sample
+    from oracle import adjoint as OA
+    from oracle.grid import Axis, Radar, make_grid
+    grid = make_grid(Radar(r.fc, r.fs, r.prf), c["M"], c["N"], c["order"],
+                     [Axis(*a) for a in c["axes"]])
+    o_err = 0.0
+    for b in np.random.default_rng(3).choice(len(th), 8, replace=False):
+        _, _, go, _ = OA.gradients(case["echo"], grid, th[b])
+        o_err = max(o_err, float(np.abs(gt[b] - go).max() / max(np.abs(go).max(), 1e-30)))
+    # refinement of the 16 jittered candidates of each target
+    t0 = time.perf_counter()
+    thr, Jr = plan.refine(echo, theta[:16 * len(case["targets"])], iters=40)
+    _sync()
+    t_ref = time.perf_counter() - t0
+    thr, Jr = thr.cpu().numpy(), Jr.cpu().numpy()
+    J0 = J.cpu().numpy()[:16 * len(case["targets"])]
+    errs = []
+    for ti, tg in enumerate(case["targets"]):
+        sl = slice(16 * ti, 16 * ti + 16)
+        b = int(np.argmax(Jr[sl]))
+        best = thr[sl][b]
+        errs.append((abs(best[0] - tg.r0), abs(best[1] - tg.v), abs(best[2] - tg.a)))
+    errs = np.array(errs)
+    out = {"metric": "DS-GRFT adjoint candidates/s (M=512): J, dJ/dtheta and dJ/decho",
+           "value": len(th) / (ms * 1e-3), "unit": "candidates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "adjoint, M=512 pulses, N=2048 bins, P=2, 16 targets at "
+                                  "-10 dB, 4096 candidates (16 jittered per target + 3840 uniform)"},
+           "grad_vs_central_diff_max_rel": fd_err, "grad_vs_oracle_max_rel": o_err,
+           "fd_candidates": int(len(idx)),
+           "refine": {"candidates": 16 * len(case["targets"]), "iters": 40,
+                      "seconds": round(t_ref, 3),
+                      "J_increase_median": float(np.median(Jr / np.maximum(J0, 1e-30))),
+                      "target_error_median": {"r0_m": float(np.median(errs[:, 0])),
+                                              "v_mps": float(np.median(errs[:, 1])),
+                                              "a_mps2": float(np.median(errs[:, 2]))},
+                      "target_error_max": {"r0_m": float(errs[:, 0].max()),
+                                           "v_mps": float(errs[:, 1].max()),
+                                           "a_mps2": float(errs[:, 2].max())},
+                      "fine_steps": {"dr_m": plan.dr, "dv_mps": plan.step[0],
+                                     "da_mps2": plan.step[1]}}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_jerk(args):
+    """M=2048, P=3 search on 64 coarse cells (the 4 targets' cells + 60
+    seeded random ones): MFMA forms vs the plain FP32 form."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_06788_amd.plan import Plan
+    case = synth.config_case(5)
+    c = synth.CONFIGS[5]
+    r = c["radar"]
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"])
+    echo = torch.from_numpy(case["echo"]).cuda()
+
+    def cell_of(tg):
+        ks = []
+        for p, val in enumerate((tg.v, tg.a, tg.j)):
+            k = int(np.floor((val / plan.step[p] - plan.i_lo[p] + 0.5) / plan.R))
+            ks.append(min(max(k, 0), plan.K[p] - 1))
+        return (ks[2] * plan.K[1] + ks[1]) * plan.K[0] + ks[0]
+    tcells = [cell_of(t) for t in case["targets"]]
+    rng = np.random.Generator(np.random.PCG64(1005))
+    others = [int(x) for x in rng.choice(plan.n_coarse, 60, replace=False)]
+    cells = torch.tensor(tcells + others, dtype=torch.int64, device="cuda")
+    n = cells.numel()
+    cp = float(n) * plan.rows * plan.n_fine * plan.M
+    res = {}
+    for form, split in (("f16", 1), ("bf16", 1), ("bf16", 3)):
+        plan.search(echo, form, split, cells=cells[:1])
+        _sync()
+        t0 = time.perf_counter()
+        pm, af = plan.search(echo, form, split, cells=cells)
+        _sync()
+        dt = time.perf_counter() - t0
+        res[f"{form}x{split}"] = {"cells_pulses_per_s": cp / dt, "s": round(dt, 3),
+                                  "target_cell_max": [float(pm[i].max()) for i in range(4)]}
+        log(f"{form}x{split}: {dt:.2f} s, {cp / dt:.3e} cells*pulses/s")
+    plan.search(echo, "f32", 1, cells=cells[:1])
+    _sync()
+    t0 = time.perf_counter()
+    pm32, _ = plan.search(echo, "f32", 1, cells=cells[:2])
+    _sync()
+    dt = time.perf_counter() - t0
+    res["f32x1"] = {"cells_pulses_per_s": 2 * plan.rows * plan.n_fine * plan.M / dt,
+                    "sample_cells": 2, "s": round(dt, 3)}
+    out = {"metric": "DS-GRFT cells·pulses/s (M=2048, P=3, 64-coarse-cell subset)",
+           "value": res["f16x1"]["cells_pulses_per_s"], "unit": "cells·pulses/s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+           "config": {"workload": "third-order search, M=2048 pulses, N=8192 bins, v +-900, "
+                                  "a +-100, j +-20; 64 of 1708224 coarse cells (4 target cells + "
+                                  "60 seeded) x 10^6 fine cells x 8192 rows",
+                      "cells": n * plan.rows * plan.n_fine, "pulses": plan.M},
+           "forms": res,
+           "speedup_vs_f32": {k: v["cells_pulses_per_s"] / res["f32x1"]["cells_pulses_per_s"]
+                              for k, v in res.items() if k != "f32x1"}}
     print(json.dumps(out), flush=True)
 
 

@@ -82,3 +82,74 @@ def test_config2_fp32_plain_and_mfma_sampled():
         pmn, afn = remap(pm.cpu().numpy()), remap(af.cpu().numpy())
         _check_rows(pmn, afn, case["echo"], grid, list(idx), rows, tol)
     assert sub
+
+
+def test_config4_adjoint_full_size():
+    """4096 candidates at the M=512, N=2048 workload: analytic gradients vs
+    central differences of the device objective, and vs the oracle on a
+    sample; J on lattice points equals the search's power map."""
+    from oracle import adjoint as OA
+    case, plan, grid, echo = _setup(4)
+    c = synth.CONFIGS[4]
+    rng = np.random.Generator(np.random.PCG64(1004))
+    th = synth.adjoint_candidates(rng, c["radar"], c["M"], c["N"], case["targets"],
+                                  c["v"], c["a"])
+    assert th.shape == (4096, 3)
+    theta = torch.from_numpy(th)
+    J, saved = plan.adjoint_forward(echo, theta)
+    gJ = torch.ones(len(th), dtype=torch.float64, device="cuda")
+    gt, _ = plan.adjoint_backward(echo, theta, saved, gJ, want_echo=False)
+    gt = gt.cpu().numpy()
+    # central differences on the device, candidates away from coarse-cell edges
+    hs = np.array([1e-4 * grid.dr, 1e-4 * grid.steps[0], 1e-4 * grid.steps[1]])
+    inside = np.ones(len(th), dtype=bool)
+    for p in (0, 1):
+        u = th[:, p + 1] / grid.steps[p] - grid.i_lo[p] + 0.5
+        fr = (u / grid.R) % 1.0
+        inside &= (fr > 0.01) & (fr < 0.99)
+    idx = np.nonzero(inside)[0]
+    assert len(idx) > 3500
+    for q in range(3):
+        e = np.zeros(3)
+        e[q] = hs[q]
+        Jp, _ = plan.adjoint_forward(echo, torch.from_numpy(th[idx] + e))
+        Jm, _ = plan.adjoint_forward(echo, torch.from_numpy(th[idx] - e))
+        fd = (Jp.cpu().numpy() - Jm.cpu().numpy()) / (2 * hs[q])
+        scale = np.abs(gt[idx, q]).max()
+        assert np.abs(fd - gt[idx, q]).max() <= 1e-4 * scale + 1e-7 * J.cpu().numpy()[idx].max() / hs[q]
+    # oracle on a sample
+    Jn = J.cpu().numpy()
+    for b in np.random.default_rng(3).choice(len(th), 12, replace=False):
+        Jo, _, go, _ = OA.gradients(case["echo"], grid, th[b])
+        assert Jn[b] == pytest.approx(Jo, rel=1e-9, abs=1e-9 * Jo + 1e-6)
+        np.testing.assert_allclose(gt[b], go, rtol=1e-7, atol=1e-9 * np.abs(go).max() + 1e-9)
+
+
+def test_config5_jerk_search_subset():
+    """P = 3 at M=2048, N=8192 on two coarse cells: the reported maximum of
+    each sampled row equals the oracle at the reported cell, and no sampled
+    fine cell of the row exceeds it (beyond the fp16 tolerance)."""
+    case, plan, grid, echo = _setup(5)
+    rng = np.random.default_rng(55)
+    cells = torch.tensor(sorted(rng.choice(plan.n_coarse, 2, replace=False).tolist()),
+                         dtype=torch.int64)
+    pm, af = plan.search(echo, "f16", 1, cells=cells)
+    pm32, af32 = plan.search(echo, "f32", 1, cells=cells)
+    pm, af = pm.cpu().numpy(), af.cpu().numpy()
+    pm32, af32 = pm32.cpu().numpy(), af32.cpu().numpy()
+    tol = 1e-3
+    e = case["echo"].astype(np.complex128)
+    for ci, k in enumerate(cells.tolist()):
+        rows = rng.choice(plan.rows, 3, replace=False)
+        for r in rows:
+            probe = np.unique(np.concatenate([rng.choice(plan.n_fine, 3000, replace=False),
+                                              [af[ci, r], af32[ci, r]]]))
+            y = OT.dsgrft_cell(e, grid, k, rows=[int(r)], fine=probe)[0]
+            P = np.abs(y) ** 2
+            scale = max(P.max(), float(pm[ci, r]))
+            at = P[np.searchsorted(probe, af[ci, r])]
+            assert abs(at - pm[ci, r]) <= tol * scale
+            assert P.max() <= pm[ci, r] + 2 * tol * scale
+            at32 = P[np.searchsorted(probe, af32[ci, r])]
+            assert abs(at32 - pm32[ci, r]) <= 1e-5 * scale
+            assert P.max() <= pm32[ci, r] + 2e-5 * scale
