@@ -22,6 +22,8 @@ Modules
             design notes).
   brute     multi-precision direct evaluation from physical parameters
             (independent of the integer numerator formula) for tiny inputs.
+  lowp      float64 model of the 8-bit float (OCP E4M3) form of the fine
+            search: operand rounding, power-of-two scales, split products.
 
 Parity status: every function here is pinned by a CPU test (brute force,
 closed forms, invariants, or a library routine); see tests/test_oracle_*.py.
