@@ -201,7 +201,9 @@ def main():
                                          "argmax_checked": clear}
     # ---- other forms: one warm step each ----------------------------------
     if not args.no_sweep:
-        for form, split in (("bf16", 3), ("bf16", 1), ("f16", 3)):
+        for form, split in (("f16", 2), ("f16", 3), ("f16", 4), ("bf16", 1), ("bf16", 2),
+                            ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3),
+                            ("fp8", 4)):
             if (form, split) == (args.form, args.split):
                 continue
             step(form, split, n=16)
@@ -233,6 +235,7 @@ def main():
     log(f"f32 plain: {f32_rate:.3e} cells*pulses/s on {n32} cells")
     ok_forms = {k: v for k, v in forms.items()
                 if k != "f32x1" and v["rel_err"] <= 1e-3 and v["argmax_bad"] == 0}
+    fastest = max(ok_forms, key=lambda k: ok_forms[k]["cells_pulses_per_s"]) if ok_forms else None
 
     # ---- CPU baseline: the oracle on a bounded sample ------------------------
     cpu = None
@@ -274,6 +277,9 @@ def main():
         "detections": int(count),
         "forms": forms,
         "forms_within_1e-3": sorted(ok_forms),
+        "fastest_within_1e-3": None if fastest is None else {
+            "form": fastest, "cells_pulses_per_s": ok_forms[fastest]["cells_pulses_per_s"],
+            "speedup_vs_f32": round(ok_forms[fastest]["cells_pulses_per_s"] / f32_rate, 2)},
     }
     print(json.dumps(out), flush=True)
 

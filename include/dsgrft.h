@@ -56,15 +56,21 @@ typedef enum {
   DSGRFT_E_CAPACITY = 5      /* output list too small; true count reported     */
 } dsgrft_status;
 
-/* Arithmetic of the fine search (the GFT stage).  FP32 runs on the vector
- * ALUs; the others on MFMA with FP32 accumulation.  `split` = 1 uses one
- * rounding of each operand; split = 3 adds the hi*lo and lo*hi correction
- * products of a hi+lo split of both operands. */
+/* Arithmetic of the fine search (the GFT stage, eq. (44)).  FP32 runs on the
+ * vector ALUs; the others on MFMA with FP32 accumulation.  Both operands (the
+ * fine phasors F and the gathered rows G) are split as x = hi + lo, and
+ * `split` (1..4) selects the products summed: 1: Fh Gh; 2: + Fl Gh;
+ * 3: + Fh Gl; 4: + Fl Gl.
+ * FP8 is OCP e4m3 with power-of-two block scales: F is stored as
+ * e4m3(256 F) (lo: e4m3(16 (256 F - hi))), and every (gathered unit, range
+ * row) gets the scale 2^(8-e) where 2^(e-1) <= the row's largest |Re|/|Im|
+ * echo component < 2^e.  Echo components must stay below 2^100 in
+ * magnitude for this form. */
 typedef enum {
-  DSGRFT_FORM_F32 = 0,   /* plain FP32 (speed baseline)             */
-  DSGRFT_FORM_F16 = 1,   /* fp16 x fp16 -> fp32, split 1 or 3       */
-  DSGRFT_FORM_BF16 = 2,  /* bf16 x bf16 -> fp32, split 1 or 3       */
-  DSGRFT_FORM_FP8 = 3    /* fp8 e4m3, per-row scale, split 1 or 3   */
+  DSGRFT_FORM_F32 = 0,   /* plain FP32 (speed baseline), split 1    */
+  DSGRFT_FORM_F16 = 1,   /* fp16 x fp16 -> fp32, split 1..4         */
+  DSGRFT_FORM_BF16 = 2,  /* bf16 x bf16 -> fp32, split 1..4         */
+  DSGRFT_FORM_FP8 = 3    /* e4m3 x e4m3 (scaled) -> fp32, split 1..4 */
 } dsgrft_form;
 
 typedef struct {

@@ -61,12 +61,19 @@ dsgrft_status check_form(dsgrft_form form, int split) {
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_F16:
     case DSGRFT_FORM_BF16:
-      return (split == 1 || split == 3) ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_FP8:
-      return (split == 1 || split == 3) ? DSGRFT_E_UNSUPPORTED : DSGRFT_E_INVALID;
+      return (split >= 1 && split <= 4) ? DSGRFT_OK : DSGRFT_E_INVALID;
     default:
       return DSGRFT_E_INVALID;
   }
+}
+
+// Bytes written per gathered sample: complex64, or 2 / 4 planes (lo parts
+// of G from split 3 on) of 2-byte or 1-byte components.
+double gather_bytes(dsgrft_form form, int split) {
+  if (form == DSGRFT_FORM_F32) return 8.0;
+  const double planes = split >= 3 ? 4.0 : 2.0;
+  return planes * (form == DSGRFT_FORM_FP8 ? 1.0 : 2.0);
 }
 
 // Stages a0..a4 over n listed cells, batch by batch.  pmax/argf may be NULL
@@ -88,7 +95,7 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
       auto &pr = p->prof;
       const bool tg = pr.ng < pr.cap, tf = pr.nf < pr.cap;
       const double samples = (double)nu * p->rows * p->M;
-      const double bg = form == DSGRFT_FORM_F32 ? 8.0 : (split == 1 ? 4.0 : 8.0);
+      const double bg = gather_bytes(form, split);
       if (tg) DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng], s));
       if (form == DSGRFT_FORM_F32)
         DS_TRY(launch_gather_f32(p, echo, nu, s));
@@ -260,6 +267,8 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   if (dalloc(&p->F32, (size_t)p->Mp * p->Cp * sizeof(float2), tot) != hipSuccess ||
       dalloc(&p->F16, f16b, tot) != hipSuccess ||
       dalloc(&p->FBF16, f16b, tot) != hipSuccess ||
+      dalloc(&p->F8, (size_t)4 * p->Cp * p->Mp, tot) != hipSuccess ||
+      dalloc(&p->g_scale, (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->u_off, (size_t)bu * p->Mp * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->u_psi, (size_t)bu * p->Mp * sizeof(float2), tot) != hipSuccess ||
       dalloc((char **)&p->G, (size_t)bu * per_unit, tot) != hipSuccess ||

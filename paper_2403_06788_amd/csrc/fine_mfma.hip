@@ -8,22 +8,30 @@
 // with F the fine phase matrix shared by all units (plan table) and G the
 // gathered, de-ramped slow-time rows (stages a1 + a2).  As real MFMA products:
 //   Yr = Fr Gr - Fi Gi,  Yi = Fr Gi + Fi Gr,
-// and with the hi+lo split of both operands (split = 3) the three products
-// hi*hi + hi*lo + lo*hi of each, all accumulated in FP32.
+// all accumulated in FP32.  With both operands split into hi + lo parts the
+// products taken are, by split count: 1: Fh Gh; 2: + Fl Gh; 3: + Fh Gl;
+// 4: + Fl Gl.
+//
+// Operand formats: fp16 and bf16 (v_mfma_f32_32x32x16, 16 pulses per K
+// step, 1 KiB fragments) and OCP e4m3 (v_mfma_scale_f32_32x32x64_f8f6f4, 64
+// pulses per K step, 2 KiB fragments) whose E8M0 block scales carry the
+// power-of-two factors of the 8-bit encoding: 2^-8 (hi) and 2^-12 (lo) for
+// the fine table, and a per-(unit, row) exponent for G.  The instruction
+// takes the scale of row i's K block from lanes i and i + 32; both lanes
+// carry the row's scale, so one scale per row is exact.
 //
 // Work decomposition: a workgroup of 2 x 2 waves computes a 128 (fine) x
 // 64 WNB (row) tile of one unit; each wave a 64 x 32 WNB sub-tile as 2 x WNB
-// blocks of v_mfma_f32_32x32x16 (fine cells on the MFMA rows, range rows on
-// its columns), WNB = 4 for one product per operand pair and 2 for the
-// three-product split.  The wider wave tile reuses each fragment read from
-// LDS for more MFMAs: the kernel is bound by LDS traffic (copies in plus
-// fragment reads), not by the MFMA issue.  Accumulators live in AGPRs.
-// Operand fragments are stored pre-swizzled in global memory.
+// blocks of 32 x 32 MFMAs (fine cells on the MFMA rows, range rows on its
+// columns).  The wider wave tile reuses each fragment read from LDS for more
+// MFMAs: the kernel is bound by LDS traffic (copies in plus fragment reads),
+// not by the MFMA issue.  Accumulators live in AGPRs.  Operand fragments are
+// stored pre-swizzled in global memory.
 //
-// Pipeline (one K step = 16 pulses):
+// Pipeline (one K step):
 //  * operands move global -> LDS with direct LDS-DMA loads (16 bytes per
-//    lane; one 1 KiB fragment per wave and chunk row), into a ring of NST
-//    stages issued NST - 1 steps ahead;
+//    lane; one 1 KiB fragment half per wave and chunk row), into a ring of
+//    NST stages issued NST - 1 steps ahead;
 //  * each wave reads the next step's fragments from LDS into a second
 //    register set while the MFMAs of the current step run, so neither the
 //    copy latency nor the LDS latency sits in front of the MFMAs;
@@ -40,39 +48,58 @@
 // (power bits << 32 | ~fine) into the per-(cell, row) result: the largest
 // power wins and equal powers resolve to the smaller fine index, whatever the
 // order of the atomics.
-#include <type_traits>
-
 #include "internal.h"
 
 namespace {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef int i8v __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
-typedef const __attribute__((address_space(1))) void glob_void;
 
-template <typename T>
-struct Mfma;
-template <>
-struct Mfma<_Float16> {
-  static __device__ inline f16v run(uint4 a, uint4 b, f16v c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a),
-                                                  __builtin_bit_cast(h8, b), c, 0, 0, 0);
-  }
-};
-template <>
-struct Mfma<__bf16> {
-  static __device__ inline f16v run(uint4 a, uint4 b, f16v c) {
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, a),
-                                                   __builtin_bit_cast(b8, b), c, 0, 0, 0);
-  }
+// One lane's share of an operand fragment: FR 16-byte chunks.
+template <int FR>
+struct Frag {
+  uint4 v[FR];
 };
 
-__device__ inline uint4 neg16(uint4 a) {
-  return make_uint4(a.x ^ 0x80008000u, a.y ^ 0x80008000u, a.z ^ 0x80008000u,
-                    a.w ^ 0x80008000u);
+__device__ inline uint4 xor4(uint4 a, unsigned m) {
+  return make_uint4(a.x ^ m, a.y ^ m, a.z ^ m, a.w ^ m);
 }
+
+struct OpF16 {
+  static constexpr int FR = 1, KSTEP = 16;
+  static __device__ inline f16v mma(const Frag<1> &a, const Frag<1> &b, f16v c, int, int) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8, a.v[0]),
+                                                  __builtin_bit_cast(h8, b.v[0]), c, 0, 0, 0);
+  }
+  static __device__ inline Frag<1> neg(const Frag<1> &a) { return {{xor4(a.v[0], 0x80008000u)}}; }
+};
+
+struct OpBF16 {
+  static constexpr int FR = 1, KSTEP = 16;
+  static __device__ inline f16v mma(const Frag<1> &a, const Frag<1> &b, f16v c, int, int) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8, a.v[0]),
+                                                   __builtin_bit_cast(b8, b.v[0]), c, 0, 0, 0);
+  }
+  static __device__ inline Frag<1> neg(const Frag<1> &a) { return {{xor4(a.v[0], 0x80008000u)}}; }
+};
+
+struct OpF8 {
+  static constexpr int FR = 2, KSTEP = 64;
+  // sa, sb: E8M0 codes (2^(code - 127)) of the A (fine) and B (row) blocks
+  static __device__ inline f16v mma(const Frag<2> &a, const Frag<2> &b, f16v c, int sa, int sb) {
+    const i8v A = {(int)a.v[0].x, (int)a.v[0].y, (int)a.v[0].z, (int)a.v[0].w,
+                   (int)a.v[1].x, (int)a.v[1].y, (int)a.v[1].z, (int)a.v[1].w};
+    const i8v B = {(int)b.v[0].x, (int)b.v[0].y, (int)b.v[0].z, (int)b.v[0].w,
+                   (int)b.v[1].x, (int)b.v[1].y, (int)b.v[1].z, (int)b.v[1].w};
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, B, c, 0, 0, 0, sa, 0, sb);
+  }
+  static __device__ inline Frag<2> neg(const Frag<2> &a) {
+    return {{xor4(a.v[0], 0x80808080u), xor4(a.v[1], 0x80808080u)}};
+  }
+};
 
 __device__ inline unsigned long long umax64(unsigned long long a,
                                             unsigned long long b) {
@@ -111,15 +138,26 @@ __device__ inline TileMap map_tile(int64_t bid, int64_t T, int NT, int FT, int G
   return tm;
 }
 
-template <int SPLIT>
+// Tile shape and pipeline depth per operand format and split count.  A
+// stage holds NPF planes x 4 fine fragments and NPG planes x 2 WNB row
+// fragments.  Two workgroups share a CU when their rings fit in 160 KiB
+// and their registers in the 512 of a SIMD lane.
+template <class Op, int SPLIT>
 struct Cfg {
-  static constexpr int NP = SPLIT == 1 ? 2 : 4;   // operand planes
-  static constexpr int WNB = 2;                   // row blocks per wave
-  static constexpr int NBLK = 4 + 2 * WNB;        // fragments per plane/stage
-  static constexpr int NST = SPLIT == 1 ? 4 : 3;  // LDS ring stages
-  static constexpr int MINB = SPLIT == 1 ? 2 : 1; // workgroups per CU
-  static constexpr int CH = NP * NBLK * 64;       // 16-byte chunks per stage
+  static constexpr int FR = Op::FR;
+  static constexpr int NPF = SPLIT >= 2 ? 4 : 2;  // fine-table planes
+  static constexpr int NPG = SPLIT >= 3 ? 4 : 2;  // gathered planes
+  static constexpr int WNB = (FR == 1 || SPLIT == 1) ? 2 : 1;
+  static constexpr int NBG = 2 * WNB;             // row fragments per plane
+  static constexpr int NFRAG = NPF * 4 + NPG * NBG;
+  static constexpr int CH = NFRAG * FR * 64;      // 16-byte chunks per stage
   static constexpr int CPT = CH / 256;            // chunks per thread
+  static constexpr int STAGE = CH * 16;
+  static constexpr int NST = 4 * STAGE <= 80 * 1024 ? 4 : 3;
+  // two workgroups per CU also need two register sets: split 1 only
+  static constexpr int MINB = (SPLIT == 1 && NST * STAGE <= 80 * 1024) ? 2 : 1;
+  static_assert(CH % 256 == 0, "stage must split evenly over 256 threads");
+  static_assert(NST * STAGE <= 160 * 1024, "ring exceeds LDS");
 };
 
 // Wait until at most `ahead` stages of this wave's copies are in flight,
@@ -143,92 +181,136 @@ __device__ inline void wait_copies_barrier(int ahead) {
 
 // Instruction order inside one K step: the next step's LDS reads first, then
 // the MFMAs of this step.
-template <int NP, int WNB, int SPLIT>
+template <class CF, int SPLIT>
 __device__ inline void order_step() {
-  __builtin_amdgcn_sched_group_barrier(0x100, NP * (2 + WNB), 0);  // DS reads
-  __builtin_amdgcn_sched_group_barrier(0x008, SPLIT * 8 * WNB, 0); // MFMAs
+  __builtin_amdgcn_sched_group_barrier(0x100, (CF::NPF * 2 + CF::NPG * CF::WNB) * CF::FR, 0);
+  __builtin_amdgcn_sched_group_barrier(0x008, SPLIT * 8 * CF::WNB, 0);
 }
 
-template <int NP, int WNB>
+template <class CF>
 __device__ inline void read_frags(const uint4 *__restrict__ slot, int wf, int wn,
-                                  int lane, uint4 (&a)[NP][2], uint4 (&b)[NP][WNB]) {
-  constexpr int NBLK = 4 + 2 * WNB;
+                                  int lane, Frag<CF::FR> (&a)[CF::NPF][2],
+                                  Frag<CF::FR> (&b)[CF::NPG][CF::WNB]) {
+  constexpr int FR = CF::FR;
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
+  for (int p = 0; p < CF::NPF; ++p)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[p][i] = slot[(p * NBLK + wf * 2 + i) * 64 + lane];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < WNB; ++j)
-      b[p][j] = slot[(p * NBLK + 4 + wn * WNB + j) * 64 + lane];
-  }
+      for (int h = 0; h < FR; ++h)
+        a[p][i].v[h] = slot[((p * 4 + wf * 2 + i) * FR + h) * 64 + lane];
+#pragma unroll
+  for (int p = 0; p < CF::NPG; ++p)
+#pragma unroll
+    for (int j = 0; j < CF::WNB; ++j)
+#pragma unroll
+      for (int h = 0; h < FR; ++h)
+        b[p][j].v[h] =
+            slot[((CF::NPF * 4 + p * CF::NBG + wn * CF::WNB + j) * FR + h) * 64 + lane];
 }
 
 // Empty asm "redefining" a fragment set: MFMAs that consume the set cannot
 // be scheduled above this point.  Placed after each step's barrier, it keeps
 // the next step's MFMAs (and the waits for their LDS reads) out of the
 // current step.
-template <int NP, int WNB>
-__device__ inline void pin(uint4 (&a)[NP][2], uint4 (&b)[NP][WNB]) {
+template <int FR>
+__device__ inline void pin1(Frag<FR> &f) {
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      asm volatile("" : "+v"(a[p][i].x), "+v"(a[p][i].y), "+v"(a[p][i].z), "+v"(a[p][i].w));
-#pragma unroll
-    for (int j = 0; j < WNB; ++j)
-      asm volatile("" : "+v"(b[p][j].x), "+v"(b[p][j].y), "+v"(b[p][j].z), "+v"(b[p][j].w));
-  }
+  for (int h = 0; h < FR; ++h)
+    asm volatile("" : "+v"(f.v[h].x), "+v"(f.v[h].y), "+v"(f.v[h].z), "+v"(f.v[h].w));
 }
 
-template <typename T, int SPLIT, int NP, int WNB>
-__device__ inline void mma_step(const uint4 (&a)[NP][2], const uint4 (&b)[NP][WNB],
-                                f16v (&accR)[2][WNB], f16v (&accI)[2][WNB]) {
+template <class CF>
+__device__ inline void pin(Frag<CF::FR> (&a)[CF::NPF][2], Frag<CF::FR> (&b)[CF::NPG][CF::WNB]) {
+#pragma unroll
+  for (int p = 0; p < CF::NPF; ++p)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) pin1<CF::FR>(a[p][i]);
+#pragma unroll
+  for (int p = 0; p < CF::NPG; ++p)
+#pragma unroll
+    for (int j = 0; j < CF::WNB; ++j) pin1<CF::FR>(b[p][j]);
+}
+
+// sa[0/1]: fine-table hi/lo scale codes; sb[0/1][j]: row block j's hi/lo.
+template <class Op, class CF, int SPLIT>
+__device__ inline void mma_step(const Frag<CF::FR> (&a)[CF::NPF][2],
+                                const Frag<CF::FR> (&b)[CF::NPG][CF::WNB],
+                                f16v (&accR)[2][CF::WNB], f16v (&accI)[2][CF::WNB],
+                                const int (&sa)[2], const int (&sb)[2][CF::WNB]) {
 #pragma unroll
   for (int s = 0; s < SPLIT; ++s) {
-    const int pa = (s == 2) ? 2 : 0;  // hi*hi, hi*lo, lo*hi
-    const int pb = (s == 1) ? 2 : 0;
+    const int la = (s == 1 || s == 3) ? 1 : 0;  // fine table lo in passes 1, 3
+    const int lb = (s >= 2) ? 1 : 0;            // gathered lo in passes 2, 3
+    const int pa = 2 * la, pb = 2 * lb;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const uint4 nfi = neg16(a[pa + 1][i]);
+      const Frag<CF::FR> nfi = Op::neg(a[pa + 1][i]);
 #pragma unroll
-      for (int j = 0; j < WNB; ++j) {
-        accR[i][j] = Mfma<T>::run(a[pa][i], b[pb][j], accR[i][j]);
-        accR[i][j] = Mfma<T>::run(nfi, b[pb + 1][j], accR[i][j]);
-        accI[i][j] = Mfma<T>::run(a[pa][i], b[pb + 1][j], accI[i][j]);
-        accI[i][j] = Mfma<T>::run(a[pa + 1][i], b[pb][j], accI[i][j]);
+      for (int j = 0; j < CF::WNB; ++j) {
+        const int x = sa[la], y = sb[lb][j];
+        accR[i][j] = Op::mma(a[pa][i], b[pb][j], accR[i][j], x, y);
+        accR[i][j] = Op::mma(nfi, b[pb + 1][j], accR[i][j], x, y);
+        accI[i][j] = Op::mma(a[pa][i], b[pb + 1][j], accI[i][j], x, y);
+        accI[i][j] = Op::mma(a[pa + 1][i], b[pb][j], accI[i][j], x, y);
       }
     }
   }
 }
 
-template <typename T, int SPLIT>
-__global__ __launch_bounds__(256, Cfg<SPLIT>::MINB) void k_fine_mfma(
+// F, G: operand fragments; KS: K steps (Mp / Op::KSTEP); gsc: per-(unit,
+// row) scale codes of G (8-bit form only); fsc: the fine table's hi scale
+// code (lo is 4 below).
+template <class Op, int SPLIT>
+__global__ __launch_bounds__(256, (Cfg<Op, SPLIT>::MINB)) void k_fine_mfma(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
+    const int32_t *__restrict__ gsc, int fsc,
     unsigned long long *__restrict__ packed, float *__restrict__ full, int FB,
-    int NB, int KB, int64_t nunits, int64_t unit0, int R3, int C, int rows,
-    int GN) {
-  using CF = Cfg<SPLIT>;
-  constexpr int NP = CF::NP, NST = CF::NST, CH = CF::CH, CPT = CF::CPT;
-  constexpr int WNB = CF::WNB, NBLK = CF::NBLK;
+    int NB, int KS, int rows_p, int64_t nunits, int64_t unit0, int R3, int C,
+    int rows, int GN) {
+  using CF = Cfg<Op, SPLIT>;
+  constexpr int FR = CF::FR, NPF = CF::NPF, NPG = CF::NPG, NST = CF::NST;
+  constexpr int CH = CF::CH, CPT = CF::CPT, WNB = CF::WNB, NBG = CF::NBG;
   __shared__ uint4 lds[NST][CH];
 
-  const int NT = NB / (2 * WNB), FT = FB >> 2;
+  const int NT = NB / NBG, FT = FB >> 2;
   const TileMap tm = map_tile(blockIdx.x, nunits * NT * FT, NT, FT, GN);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wf = wave & 1, wn = wave >> 1;
   const int wbase = tid & ~63;
 
+  // block scales (8-bit form); the asm consumes the loaded values here so
+  // that their wait is not placed after the first copies are in flight
+  int sa[2] = {fsc, fsc - 4};
+  int sb[2][WNB];
+#pragma unroll
+  for (int j = 0; j < WNB; ++j) {
+    sb[0][j] = 0;
+    if (gsc != nullptr) {
+      const int n = (tm.nt * NBG + wn * WNB + j) * 32 + (lane & 31);
+      sb[0][j] = gsc[tm.u * rows_p + n];
+      asm volatile("" : "+v"(sb[0][j]));
+    }
+    sb[1][j] = sb[0][j] - 4;
+  }
+
   // Global source of this thread's chunks (16-byte units).  Chunk c of a
-  // stage: lane c % 64, block (c / 64) % NBLK (0-3 fine, then rows), plane
-  // (c / 64) / NBLK.
+  // stage: lane c % 64, half (c / 64) % FR, fragment (c / 64) / FR: fine
+  // fragments first (plane-major, 4 per plane), then row fragments (NBG per
+  // plane).
   const uint4 *src[CPT];
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const int c = tid + 256 * j;
-    const int ln = c & 63, blk = (c >> 6) % NBLK, plane = (c >> 6) / NBLK;
-    src[j] = (blk < 4)
-                 ? F + (((int64_t)plane * FB + tm.ft * 4 + blk) * KB) * 64 + ln
-                 : G + (((tm.u * NP + plane) * NB + tm.nt * 2 * WNB + (blk - 4)) * (int64_t)KB) * 64 + ln;
+    const int ln = c & 63, h = (c >> 6) % FR, fi = (c >> 6) / FR;
+    if (fi < NPF * 4) {
+      const int plane = fi >> 2, blk = fi & 3;
+      src[j] = F + (((int64_t)plane * FB + tm.ft * 4 + blk) * KS) * (FR * 64) + h * 64 + ln;
+    } else {
+      const int gi = fi - NPF * 4, plane = gi / NBG, blk = gi % NBG;
+      src[j] = G + (((tm.u * NPG + plane) * NB + tm.nt * NBG + blk) * (int64_t)KS) * (FR * 64) +
+               h * 64 + ln;
+    }
   }
   // Copy K step `stage` into its ring slot: global_load_lds_dwordx4 writes
   // lane l's 16 bytes to LDS at M0 + 16 l.  It is issued from inline
@@ -243,7 +325,7 @@ __global__ __launch_bounds__(256, Cfg<SPLIT>::MINB) void k_fine_mfma(
     for (int j = 0; j < CPT; ++j) {
       const unsigned la = __builtin_amdgcn_readfirstlane(
           (unsigned)(size_t)(lds_void *)&dst[wbase + 256 * j]);
-      const uint4 *g = src[j] + (int64_t)stage * 64;
+      const uint4 *g = src[j] + (int64_t)stage * (FR * 64);
       unsigned saved_m0;
       asm volatile(
           "s_mov_b32 %0, m0\n\t"
@@ -267,14 +349,14 @@ __global__ __launch_bounds__(256, Cfg<SPLIT>::MINB) void k_fine_mfma(
       accI[i][j] = f16v{};
     }
 
-  const int nkt = KB;
+  const int nkt = KS;
   // prologue: stages 0 .. NST-2 in flight, stage 0 visible, its fragments read
 #pragma unroll
   for (int s = 0; s < NST - 1; ++s)
     if (s < nkt) issue(s);
   wait_copies_barrier<CPT>((nkt - 1 < NST - 2) ? nkt - 1 : NST - 2);
-  uint4 a0[NP][2], b0[NP][WNB], a1[NP][2], b1[NP][WNB];
-  read_frags<NP, WNB>(lds[0], wf, wn, lane, a0, b0);
+  Frag<FR> a0[NPF][2], b0[NPG][WNB], a1[NPF][2], b1[NPG][WNB];
+  read_frags<CF>(lds[0], wf, wn, lane, a0, b0);
 
   // One K step: make stage kt+1 visible, read its fragments into (an, bn),
   // refill the slot freed one step ago, then the MFMAs of step kt.
@@ -284,11 +366,11 @@ __global__ __launch_bounds__(256, Cfg<SPLIT>::MINB) void k_fine_mfma(
     if (kt_ + 1 < nkt) {                                                       \
       const int last = (nkt - 1 < kt_ + NST - 2) ? nkt - 1 : kt_ + NST - 2;    \
       wait_copies_barrier<CPT>(last - (kt_ + 1));                              \
-      pin<NP, WNB>(AC, BC);                                                    \
-      read_frags<NP, WNB>(lds[(kt_ + 1) % NST], wf, wn, lane, AN, BN);         \
+      pin<CF>(AC, BC);                                                         \
+      read_frags<CF>(lds[(kt_ + 1) % NST], wf, wn, lane, AN, BN);              \
       if (kt_ + NST - 1 < nkt) issue(kt_ + NST - 1);                           \
     }                                                                          \
-    mma_step<T, SPLIT, NP, WNB>(AC, BC, accR, accI);                           \
+    mma_step<Op, CF, SPLIT>(AC, BC, accR, accI, sa, sb);                       \
   } while (0)
 
   // Steady state, branch-free: every step waits for the same number of
@@ -297,11 +379,11 @@ __global__ __launch_bounds__(256, Cfg<SPLIT>::MINB) void k_fine_mfma(
   do {                                                                         \
     const int kt_ = (KT);                                                      \
     wait_copies_barrier<CPT>(NST - 3);                                         \
-    pin<NP, WNB>(AC, BC);                                                      \
-    read_frags<NP, WNB>(lds[(kt_ + 1) % NST], wf, wn, lane, AN, BN);           \
+    pin<CF>(AC, BC);                                                           \
+    read_frags<CF>(lds[(kt_ + 1) % NST], wf, wn, lane, AN, BN);                \
     issue(kt_ + NST - 1);                                                      \
-    mma_step<T, SPLIT, NP, WNB>(AC, BC, accR, accI);                           \
-    order_step<NP, WNB, SPLIT>();                                              \
+    mma_step<Op, CF, SPLIT>(AC, BC, accR, accI, sa, sb);                       \
+    order_step<CF, SPLIT>();                                                   \
   } while (0)
   int kt = 0;
   for (; kt + NST < nkt; kt += 2) {
@@ -321,7 +403,7 @@ __global__ __launch_bounds__(256, Cfg<SPLIT>::MINB) void k_fine_mfma(
   const unsigned fbase = (unsigned)((ug % R3) * C);
 #pragma unroll
   for (int j = 0; j < WNB; ++j) {
-    const int n = (tm.nt * 2 * WNB + wn * WNB + j) * 32 + (lane & 31);
+    const int n = (tm.nt * NBG + wn * WNB + j) * 32 + (lane & 31);
     unsigned long long best = 0ull;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -360,15 +442,29 @@ __global__ void k_unpack(const unsigned long long *__restrict__ packed, int64_t 
   argf[i] = (int32_t)(0xffffffffu - (unsigned)v);
 }
 
-template <typename T, int SPLIT>
-hipError_t launch_t(dsgrft_plan p, int64_t nunits, int64_t unit0, float *full,
-                    hipStream_t s) {
-  int64_t tiles = nunits * (p->NB / (2 * Cfg<SPLIT>::WNB)) * (p->FB / 4);
-  hipLaunchKernelGGL((k_fine_mfma<T, SPLIT>), dim3((unsigned)tiles), dim3(256), 0, s,
-                     (const uint4 *)(std::is_same<T, _Float16>::value ? p->F16 : p->FBF16),
-                     (const uint4 *)p->G, p->packed, full, p->FB, p->NB, p->KB,
-                     nunits, unit0, p->R3, p->C, p->rows, 8);
+template <class Op, int SPLIT>
+hipError_t launch_t(dsgrft_plan p, const void *F, int fsc, int64_t nunits,
+                    int64_t unit0, float *full, hipStream_t s) {
+  using CF = Cfg<Op, SPLIT>;
+  int64_t tiles = nunits * (p->NB / CF::NBG) * (p->FB / 4);
+  const int32_t *gsc = Op::FR == 2 ? p->g_scale : nullptr;
+  hipLaunchKernelGGL((k_fine_mfma<Op, SPLIT>), dim3((unsigned)tiles), dim3(256), 0, s,
+                     (const uint4 *)F, (const uint4 *)p->G, gsc, fsc, p->packed, full,
+                     p->FB, p->NB, p->Mp / Op::KSTEP, p->rows_p, nunits, unit0, p->R3,
+                     p->C, p->rows, 8);
   return hipGetLastError();
+}
+
+template <class Op>
+hipError_t launch_split(dsgrft_plan p, const void *F, int fsc, int split,
+                        int64_t nunits, int64_t unit0, float *full, hipStream_t s) {
+  switch (split) {
+    case 1: return launch_t<Op, 1>(p, F, fsc, nunits, unit0, full, s);
+    case 2: return launch_t<Op, 2>(p, F, fsc, nunits, unit0, full, s);
+    case 3: return launch_t<Op, 3>(p, F, fsc, nunits, unit0, full, s);
+    case 4: return launch_t<Op, 4>(p, F, fsc, nunits, unit0, full, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -390,11 +486,15 @@ hipError_t launch_unpack(dsgrft_plan p, int64_t ncells, float *pmax,
 hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
                             int64_t nunits, int64_t unit0, float *full,
                             hipStream_t s) {
-  if (form == DSGRFT_FORM_F16)
-    return split == 1 ? launch_t<_Float16, 1>(p, nunits, unit0, full, s)
-                      : launch_t<_Float16, 3>(p, nunits, unit0, full, s);
-  if (form == DSGRFT_FORM_BF16)
-    return split == 1 ? launch_t<__bf16, 1>(p, nunits, unit0, full, s)
-                      : launch_t<__bf16, 3>(p, nunits, unit0, full, s);
-  return hipErrorInvalidValue;
+  switch (form) {
+    case DSGRFT_FORM_F16:
+      return launch_split<OpF16>(p, p->F16, 0, split, nunits, unit0, full, s);
+    case DSGRFT_FORM_BF16:
+      return launch_split<OpBF16>(p, p->FBF16, 0, split, nunits, unit0, full, s);
+    case DSGRFT_FORM_FP8:
+      // fine table: hi = e4m3(256 F) -> 2^-8 (code 119), lo -> 2^-12
+      return launch_split<OpF8>(p, p->F8, 119, split, nunits, unit0, full, s);
+    default:
+      return hipErrorInvalidValue;
+  }
 }

@@ -13,6 +13,15 @@
 //    (Mp/16) pulse blocks x 64 lanes x 8 elements; lane l holds row
 //    32 nb + l % 32 and pulses 16 kb + 8 (l / 32) + e.  One wave writes one
 //    1 KiB fragment per plane, contiguously.
+//  * 8-bit form: B-operand fragments of v_mfma_scale_f32_32x32x64_f8f6f4
+//    (OCP e4m3), K blocks of 64 pulses, 2 KiB each as two halves
+//    [e / 16][lane][e % 16], lane l holding row 32 nb + l % 32 and pulses
+//    64 kb + 32 (l / 32) + e.  Every (unit, row) has its own power-of-two
+//    scale: with mx the largest |Re S| or |Im S| over the row's walk and
+//    mx = f 2^e (f in [0.5, 1)), the row is stored as x = G 2^(8 - e),
+//    hi = e4m3(x), lo = e4m3(16 (x - hi)), and the E8M0 block-scale code
+//    119 + e (2^(e - 8)) is written per row for the MFMA.  |x| < 256 sqrt 2
+//    stays inside the e4m3 range (448).
 #include "internal.h"
 
 namespace {
@@ -108,6 +117,103 @@ __global__ __launch_bounds__(256) void k_gather_lp(
   }
 }
 
+__device__ inline uint32_t pack_e4m3(const float (&x)[4]) {
+  int v = __builtin_amdgcn_cvt_pk_fp8_f32(x[0], x[1], 0, false);
+  v = __builtin_amdgcn_cvt_pk_fp8_f32(x[2], x[3], v, true);
+  return (uint32_t)v;
+}
+
+// 16 (x - e4m3(x)) for the four bytes of a packed word.
+__device__ inline void residual16(const float (&x)[4], uint32_t h, float (&r)[4]) {
+  r[0] = 16.0f * (x[0] - __builtin_amdgcn_cvt_f32_fp8((int)h, 0));
+  r[1] = 16.0f * (x[1] - __builtin_amdgcn_cvt_f32_fp8((int)h, 1));
+  r[2] = 16.0f * (x[2] - __builtin_amdgcn_cvt_f32_fp8((int)h, 2));
+  r[3] = 16.0f * (x[3] - __builtin_amdgcn_cvt_f32_fp8((int)h, 3));
+}
+
+// One workgroup per (unit, block of 32 rows): pass 1 finds each row's
+// largest component over all pulses, pass 2 writes the row block's
+// fragments (wave w: pulse blocks w, w + 4, ...).  The second pass re-reads
+// the walk, which the first pass has just brought into the caches.
+template <int NP>
+__global__ __launch_bounds__(256) void k_gather_f8(
+    const float2 *__restrict__ echo, const int32_t *__restrict__ off,
+    const float2 *__restrict__ psi, int M, int N, int Mp, int rows, int rows_p,
+    int n_begin, int NB, int KB8, uint4 *__restrict__ G,
+    int32_t *__restrict__ scale) {
+  __shared__ float red[8][32];
+  __shared__ float mul[32];
+  const int nb = (int)(blockIdx.x % NB);
+  const int64_t u = blockIdx.x / NB;
+  const int t = threadIdx.x;
+  const int32_t *uo = off + u * Mp;
+  const float2 *up = psi + u * Mp;
+  {
+    const int r = nb * 32 + (t & 31), g = t >> 5;
+    float mx = 0.f;
+    if (r < rows)
+      for (int m = g; m < M; m += 8) {
+        const float2 v = sample(echo, N, m, n_begin + r + uo[m]);
+        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+      }
+    red[g][t & 31] = mx;
+  }
+  __syncthreads();
+  if (t < 32) {
+    float mx = red[0][t];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) mx = fmaxf(mx, red[g][t]);
+    int e = 0;
+    if (mx > 0.f) (void)frexpf(mx, &e);
+    e = e < -100 ? -100 : (e > 100 ? 100 : e);
+    mul[t] = ldexpf(1.0f, 8 - e);
+    scale[u * rows_p + nb * 32 + t] = 119 + e;
+  }
+  __syncthreads();
+
+  const int lane = t & 63, w = t >> 6;
+  const int r = nb * 32 + (lane & 31);
+  const float sm = mul[lane & 31];
+  const int64_t plane = (int64_t)NB * KB8 * 128;  // uint4 per plane
+  for (int kb = w; kb < KB8; kb += 4) {
+    const int m0 = kb * 64 + 32 * (lane >> 5);
+    uint32_t rh[8], ih[8], rl[8], il[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      float xr[4], xi[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + 4 * d + q;
+        float2 v = make_float2(0.f, 0.f);
+        if (m < M && r < rows)
+          v = cmul(sample(echo, N, m, n_begin + r + uo[m]), up[m]);
+        xr[q] = v.x * sm;
+        xi[q] = v.y * sm;
+      }
+      rh[d] = pack_e4m3(xr);
+      ih[d] = pack_e4m3(xi);
+      if (NP == 4) {
+        float lr[4], li[4];
+        residual16(xr, rh[d], lr);
+        residual16(xi, ih[d], li);
+        rl[d] = pack_e4m3(lr);
+        il[d] = pack_e4m3(li);
+      }
+    }
+    const int64_t o = (((u * NP) * NB + nb) * (int64_t)KB8 + kb) * 128 + lane;
+    G[o] = make_uint4(rh[0], rh[1], rh[2], rh[3]);
+    G[o + 64] = make_uint4(rh[4], rh[5], rh[6], rh[7]);
+    G[o + plane] = make_uint4(ih[0], ih[1], ih[2], ih[3]);
+    G[o + plane + 64] = make_uint4(ih[4], ih[5], ih[6], ih[7]);
+    if (NP == 4) {
+      G[o + 2 * plane] = make_uint4(rl[0], rl[1], rl[2], rl[3]);
+      G[o + 2 * plane + 64] = make_uint4(rl[4], rl[5], rl[6], rl[7]);
+      G[o + 3 * plane] = make_uint4(il[0], il[1], il[2], il[3]);
+      G[o + 3 * plane + 64] = make_uint4(il[4], il[5], il[6], il[7]);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gather_f32(dsgrft_plan p, const float2 *echo, int64_t nunits,
@@ -129,11 +235,25 @@ hipError_t launch_mgift_out(dsgrft_plan p, const float2 *echo, int64_t nunits,
 
 hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
                             const float2 *echo, int64_t nunits, hipStream_t s) {
+  // G's lo planes enter from split 3 on (split 2 adds the fine table's lo)
+  const bool lo = split >= 3;
+  uint4 *G = (uint4 *)p->G;
+  if (form == DSGRFT_FORM_FP8) {
+    dim3 grid((unsigned)(nunits * p->NB));
+    if (lo)
+      hipLaunchKernelGGL((k_gather_f8<4>), grid, dim3(256), 0, s, echo, p->u_off,
+                         p->u_psi, p->M, p->N, p->Mp, p->rows, p->rows_p,
+                         p->n_begin, p->NB, p->KB / 4, G, p->g_scale);
+    else
+      hipLaunchKernelGGL((k_gather_f8<2>), grid, dim3(256), 0, s, echo, p->u_off,
+                         p->u_psi, p->M, p->N, p->Mp, p->rows, p->rows_p,
+                         p->n_begin, p->NB, p->KB / 4, G, p->g_scale);
+    return hipGetLastError();
+  }
   int64_t waves = nunits * p->NB * p->KB;
   dim3 grid((unsigned)((waves + 3) / 4));
-  uint4 *G = (uint4 *)p->G;
   if (form == DSGRFT_FORM_F16) {
-    if (split == 1)
+    if (!lo)
       hipLaunchKernelGGL((k_gather_lp<_Float16, 2>), grid, dim3(256), 0, s, echo,
                          p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows,
                          p->n_begin, p->NB, p->KB, nunits, G);
@@ -142,7 +262,7 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
                          p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows,
                          p->n_begin, p->NB, p->KB, nunits, G);
   } else if (form == DSGRFT_FORM_BF16) {
-    if (split == 1)
+    if (!lo)
       hipLaunchKernelGGL((k_gather_lp<__bf16, 2>), grid, dim3(256), 0, s, echo,
                          p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows,
                          p->n_begin, p->NB, p->KB, nunits, G);

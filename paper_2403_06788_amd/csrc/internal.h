@@ -72,11 +72,11 @@ struct dsgrft_plan_s {
   float2 *F32;          // [Mp][Cp] fine phasors, complex64
   uint4 *F16;           // MFMA fragments, 4 planes (re_hi, im_hi, re_lo, im_lo)
   uint4 *FBF16;         // same in bf16
-  uint4 *F8;            // fp8 e4m3 fragments (K blocks of 64), 4 planes
+  uint4 *F8;            // e4m3 fragments (K blocks of 64), same 4 planes
   int32_t *u_off;       // [batch_units][Mp] unit range offsets
   float2 *u_psi;        // [batch_units][Mp] unit de-ramp phasors
   void *G;              // gathered batch, max 8 bytes per (unit,row,pulse)
-  float *g_scale;       // [batch_units][rows_p] per-row fp8 scales
+  int32_t *g_scale;     // [batch_units][rows_p] per-row E8M0 codes (8-bit form)
   unsigned long long *packed;  // [batch_cells][rows] (power bits, ~fine)
   void *det_ws;         // detection partials
   size_t det_ws_bytes;

@@ -9,6 +9,8 @@
 //         planes (re_hi, im_hi, re_lo, im_lo) x (Cp/32) column blocks x
 //         (Mp/16) pulse blocks x 64 lanes x 8 elements, lane l holding column
 //         32 b + l % 32 and pulses 16 kb + 8 (l / 32) + e.
+//   F8    fragments of the scaled 8-bit MFMA (OCP e4m3), same planes, K
+//         blocks of 64 pulses (layout at the conversion below).
 //
 // Unit tables: for each gathered unit (coarse cell, and for P = 3 one fine
 // jerk offset) the range offset of the coarse walk (the mGIFT envelope
@@ -70,14 +72,15 @@ __global__ void k_fine_tables(int M, int Mp, int C, int Cp, int R, int P, Lat L,
   FB16[o + 2 * plane] = bits16(cbl);
   FB16[o + 3 * plane] = bits16(sbl);
   if (F8) {
-    // fp8 fragments of v_mfma_scale_f32_32x32x64_f8f6f4: 32 bytes per lane,
-    // lane l holds column 32 b + l % 32 and pulses 64 kb + 32 (l / 32) + e.
-    // hi = e4m3(256 x), lo = e4m3(16 * (256 x - hi)) (scaled back by the
-    // MFMA block scale).
+    // fp8 fragments of v_mfma_scale_f32_32x32x64_f8f6f4 (2 KiB each): lane l
+    // holds column 32 b + l % 32 and pulses 64 kb + 32 (l / 32) + e, e < 32,
+    // stored as two 1 KiB halves [e / 16][lane][e % 16].  Components are
+    // kept as x = fl32(256 F), hi = e4m3(x), lo = e4m3(16 (x - hi)); the MFMA
+    // block scales 2^-8 and 2^-12 undo the factors.
     int kb8 = m >> 6, lane8 = (f & 31) + 32 * ((m & 63) >> 5), e8 = m & 31;
     int KB8 = KB / 4;
     int64_t plane8 = (int64_t)FB * KB8 * 2048;
-    int64_t o8 = ((int64_t)fb * KB8 + kb8) * 2048 + lane8 * 32 + e8;
+    int64_t o8 = ((int64_t)fb * KB8 + kb8) * 2048 + (e8 >> 4) * 1024 + lane8 * 16 + (e8 & 15);
     float c256 = (float)(256.0 * c), s256 = (float)(256.0 * s);
     uint8_t ch8 = to_e4m3(c256), sh8 = to_e4m3(s256);
     float chf = __builtin_amdgcn_cvt_f32_fp8(ch8, 0);

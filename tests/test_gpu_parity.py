@@ -14,8 +14,9 @@ from oracle.grid import numerator, range_offset
 
 pytestmark = pytest.mark.gpu
 
-TOL = {("f32", 1): 1e-5, ("f16", 1): 1e-3, ("f16", 3): 1e-5,
-       ("bf16", 3): 1e-4, ("bf16", 1): 1e-2}
+TOL = {("f32", 1): 1e-5, ("f16", 1): 1e-3, ("f16", 2): 1e-3, ("f16", 3): 1e-5,
+       ("f16", 4): 1e-5, ("bf16", 1): 1e-2, ("bf16", 2): 1e-2, ("bf16", 3): 1e-4,
+       ("bf16", 4): 1e-4}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
