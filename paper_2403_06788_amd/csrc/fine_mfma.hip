@@ -147,7 +147,7 @@ struct Cfg {
   static constexpr int FR = Op::FR;
   static constexpr int NPF = SPLIT >= 2 ? 4 : 2;  // fine-table planes
   static constexpr int NPG = SPLIT >= 3 ? 4 : 2;  // gathered planes
-  static constexpr int WNB = (FR == 1 || SPLIT == 1) ? 2 : 1;
+  static constexpr int WNB = FR == 1 ? 2 : 1;
   static constexpr int NBG = 2 * WNB;             // row fragments per plane
   static constexpr int NFRAG = NPF * 4 + NPG * NBG;
   static constexpr int CH = NFRAG * FR * 64;      // 16-byte chunks per stage

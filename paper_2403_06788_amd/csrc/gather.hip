@@ -133,14 +133,19 @@ __device__ inline void residual16(const float (&x)[4], uint32_t h, float (&r)[4]
 
 // One workgroup per (unit, block of 32 rows): pass 1 finds each row's
 // largest component over all pulses, pass 2 writes the row block's
-// fragments (wave w: pulse blocks w, w + 4, ...).  The second pass re-reads
-// the walk, which the first pass has just brought into the caches.
-template <int NP>
+// fragments (wave w: pulse blocks w, w + 4, ...).  When they fit (STAGED),
+// the unit's offsets and de-ramp phasors are staged in LDS once; the second
+// pass re-reads the walk, which the first pass has just brought into the
+// caches.
+template <int NP, bool STAGED>
 __global__ __launch_bounds__(256) void k_gather_f8(
     const float2 *__restrict__ echo, const int32_t *__restrict__ off,
     const float2 *__restrict__ psi, int M, int N, int Mp, int rows, int rows_p,
     int n_begin, int NB, int KB8, uint4 *__restrict__ G,
     int32_t *__restrict__ scale) {
+  extern __shared__ char smem[];
+  float2 *s_psi = (float2 *)smem;              // [Mp]
+  int32_t *s_off = (int32_t *)(s_psi + Mp);     // [Mp]
   __shared__ float red[8][32];
   __shared__ float mul[32];
   const int nb = (int)(blockIdx.x % NB);
@@ -148,15 +153,37 @@ __global__ __launch_bounds__(256) void k_gather_f8(
   const int t = threadIdx.x;
   const int32_t *uo = off + u * Mp;
   const float2 *up = psi + u * Mp;
+  if (STAGED) {
+    for (int m = t; m < Mp; m += 256) {
+      s_off[m] = uo[m];
+      s_psi[m] = up[m];
+    }
+    __syncthreads();
+    uo = s_off;
+    up = s_psi;
+  }
   {
     const int r = nb * 32 + (t & 31), g = t >> 5;
-    float mx = 0.f;
-    if (r < rows)
-      for (int m = g; m < M; m += 8) {
-        const float2 v = sample(echo, N, m, n_begin + r + uo[m]);
-        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    const int base = n_begin + r;
+    float mx0 = 0.f, mx1 = 0.f, mx2 = 0.f, mx3 = 0.f;
+    if (r < rows) {
+      int m = g;
+      for (; m + 24 < M; m += 32) {
+        const float2 v0 = sample(echo, N, m, base + uo[m]);
+        const float2 v1 = sample(echo, N, m + 8, base + uo[m + 8]);
+        const float2 v2 = sample(echo, N, m + 16, base + uo[m + 16]);
+        const float2 v3 = sample(echo, N, m + 24, base + uo[m + 24]);
+        mx0 = fmaxf(mx0, fmaxf(fabsf(v0.x), fabsf(v0.y)));
+        mx1 = fmaxf(mx1, fmaxf(fabsf(v1.x), fabsf(v1.y)));
+        mx2 = fmaxf(mx2, fmaxf(fabsf(v2.x), fabsf(v2.y)));
+        mx3 = fmaxf(mx3, fmaxf(fabsf(v3.x), fabsf(v3.y)));
       }
-    red[g][t & 31] = mx;
+      for (; m < M; m += 8) {
+        const float2 v = sample(echo, N, m, base + uo[m]);
+        mx0 = fmaxf(mx0, fmaxf(fabsf(v.x), fabsf(v.y)));
+      }
+    }
+    red[g][t & 31] = fmaxf(fmaxf(mx0, mx1), fmaxf(mx2, mx3));
   }
   __syncthreads();
   if (t < 32) {
@@ -240,14 +267,18 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
   uint4 *G = (uint4 *)p->G;
   if (form == DSGRFT_FORM_FP8) {
     dim3 grid((unsigned)(nunits * p->NB));
-    if (lo)
-      hipLaunchKernelGGL((k_gather_f8<4>), grid, dim3(256), 0, s, echo, p->u_off,
-                         p->u_psi, p->M, p->N, p->Mp, p->rows, p->rows_p,
-                         p->n_begin, p->NB, p->KB / 4, G, p->g_scale);
-    else
-      hipLaunchKernelGGL((k_gather_f8<2>), grid, dim3(256), 0, s, echo, p->u_off,
-                         p->u_psi, p->M, p->N, p->Mp, p->rows, p->rows_p,
-                         p->n_begin, p->NB, p->KB / 4, G, p->g_scale);
+    const size_t lds = (size_t)p->Mp * (sizeof(float2) + sizeof(int32_t));
+    const bool staged = lds <= 48 * 1024;
+#define DS_GATHER_F8(NP, ST)                                                        \
+  hipLaunchKernelGGL((k_gather_f8<NP, ST>), grid, dim3(256), ST ? lds : 0, s, echo,  \
+                     p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows, p->rows_p,     \
+                     p->n_begin, p->NB, p->KB / 4, G, p->g_scale)
+    if (lo) {
+      if (staged) DS_GATHER_F8(4, true); else DS_GATHER_F8(4, false);
+    } else {
+      if (staged) DS_GATHER_F8(2, true); else DS_GATHER_F8(2, false);
+    }
+#undef DS_GATHER_F8
     return hipGetLastError();
   }
   int64_t waves = nunits * p->NB * p->KB;

@@ -115,3 +115,25 @@ def test_fp8_row_scale_follows_echo_scale(case):
     a = p.search_full(case["echo_dev"], "fp8", 3)
     b = p.search_full(e2, "fp8", 3)
     assert torch.equal(b, a * (4.0 ** 7))
+
+
+def test_fp8_long_slow_time():
+    """M = 4200 pulses: the 8-bit gather reads the unit tables from global
+    memory (they exceed its LDS staging size); same model bound."""
+    import synth
+    from oracle.grid import Axis, Radar, make_grid
+    from paper_2403_06788_amd.plan import Plan
+    fc, fs, prf, M, N = 4.0e7, 1.0e7, 2000.0, 4200, 48
+    radar = synth.RadarParams(fc, fs, prf)
+    rng = np.random.Generator(np.random.PCG64(77))
+    tg = synth.draw_targets(rng, radar, M, N, 1, -6.0, 1.0, (-20.0, 20.0), (0.0, 0.0), (0.0, 0.0))
+    echo = synth.make_echo(radar, M, N, tg, 1.0, rng)
+    axes = [(-20.0, 20.0)]
+    g = make_grid(Radar(fc, fs, prf), M, N, 1, [Axis(*a) for a in axes])
+    p = Plan(fc, fs, prf, M, N, 1, axes)
+    P = p.search_full(torch.from_numpy(echo).cuda(), "fp8", 3).cpu().numpy().astype(np.float64)
+    case = {"grid": g, "echo": echo}
+    Pm, Ym, E = _model(case, 3)
+    assert np.all(np.abs(P - Pm) <= 2.0 * np.abs(Ym) * E + E ** 2)
+    ref = OT.dsgrft_power(echo.astype(np.complex128), g)
+    assert np.abs(P - ref).max() / ref.max() <= FP8_TOL[3]
