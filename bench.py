@@ -26,7 +26,6 @@ METRIC = "DS-GRFT cells·pulses/s (M=1024); MFMA vs FP32 speedup at rel err≤1e
 PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
 HBM_GBPS = 8000.0
 FINE_SRC = os.path.join(ROOT, "paper_2403_06788_amd", "csrc", "fine_mfma.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fine_mfma_f16_m1024_traffic.json")
 
 
 def log(*a):
@@ -41,7 +40,7 @@ def recorded_traffic(form, split):
     """Per-launch HBM traffic of the fine kernel from the committed rocprofv3
     counter summary, or None if absent or taken on another kernel version."""
     try:
-        d = json.load(open(TRAFFIC_FILE))
+        d = json.load(open(os.path.join(ROOT, "profiles", f"fine_mfma_{form}_m1024_traffic.json")))
     except (OSError, ValueError):
         return None
     if d.get("kernel_sha") != kernel_hash() or d.get("form") != f"{form}x{split}":
