@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DS-GRFT cells·pulses/s (M=1024); MFMA vs FP32 speedup at rel err≤1e-3"
-PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
+PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3, "f32fft": 157.3}
 HBM_GBPS = 8000.0
 FINE_SRC = os.path.join(ROOT, "paper_2403_06788_amd", "csrc", "fine_mfma.hip")
 
@@ -202,7 +202,7 @@ def main():
     if not args.no_sweep:
         for form, split in (("f16", 2), ("f16", 3), ("f16", 4), ("bf16", 1), ("bf16", 2),
                             ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3),
-                            ("fp8", 4)):
+                            ("fp8", 4), ("f32fft", 1)):
             if (form, split) == (args.form, args.split):
                 continue
             step(form, split, n=16)

@@ -70,7 +70,11 @@ typedef enum {
   DSGRFT_FORM_F32 = 0,   /* plain FP32 (speed baseline), split 1    */
   DSGRFT_FORM_F16 = 1,   /* fp16 x fp16 -> fp32, split 1..4         */
   DSGRFT_FORM_BF16 = 2,  /* bf16 x bf16 -> fp32, split 1..4         */
-  DSGRFT_FORM_FP8 = 3    /* e4m3 x e4m3 (scaled) -> fp32, split 1..4 */
+  DSGRFT_FORM_FP8 = 3,   /* e4m3 x e4m3 (scaled) -> fp32, split 1..4 */
+  DSGRFT_FORM_F32_FFT = 4 /* FP32, fine velocities by a slow-time FFT as in
+                             Alg. 2 (one per fine acceleration); split 1;
+                             M a power of two in [64, 2048], else
+                             E_UNSUPPORTED */
 } dsgrft_form;
 
 typedef struct {

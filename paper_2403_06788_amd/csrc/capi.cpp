@@ -44,7 +44,7 @@ hipError_t dalloc(T **p, size_t bytes, size_t &total) {
 void release(dsgrft_plan p) {
   if (!p) return;
   void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->u_off, p->u_psi,
-                  p->G, p->g_scale, p->packed, p->det_ws, p->adj_ws};
+                  p->G, p->g_scale, p->fft_tw, p->packed, p->det_ws, p->adj_ws};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -55,10 +55,13 @@ bool on_plan_device(dsgrft_plan p) {
   return hipGetDevice(&d) == hipSuccess && d == p->device;
 }
 
-dsgrft_status check_form(dsgrft_form form, int split) {
+dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
   switch (form) {
     case DSGRFT_FORM_F32:
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
+    case DSGRFT_FORM_F32_FFT:
+      if (split != 1) return DSGRFT_E_INVALID;
+      return p->fft_tw ? DSGRFT_OK : DSGRFT_E_UNSUPPORTED;
     case DSGRFT_FORM_F16:
     case DSGRFT_FORM_BF16:
     case DSGRFT_FORM_FP8:
@@ -71,7 +74,7 @@ dsgrft_status check_form(dsgrft_form form, int split) {
 // Bytes written per gathered sample: complex64, or 2 / 4 planes (lo parts
 // of G from split 3 on) of 2-byte or 1-byte components.
 double gather_bytes(dsgrft_form form, int split) {
-  if (form == DSGRFT_FORM_F32) return 8.0;
+  if (form == DSGRFT_FORM_F32 || form == DSGRFT_FORM_F32_FFT) return 8.0;
   const double planes = split >= 3 ? 4.0 : 2.0;
   return planes * (form == DSGRFT_FORM_FP8 ? 1.0 : 2.0);
 }
@@ -97,7 +100,7 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
       const double samples = (double)nu * p->rows * p->M;
       const double bg = gather_bytes(form, split);
       if (tg) DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng], s));
-      if (form == DSGRFT_FORM_F32)
+      if (form == DSGRFT_FORM_F32 || form == DSGRFT_FORM_F32_FFT)
         DS_TRY(launch_gather_f32(p, echo, nu, s));
       else
         DS_TRY(launch_gather_lp(p, form, split, echo, nu, s));
@@ -109,6 +112,8 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
       if (tf) DS_TRY(hipEventRecord(pr.ev_f[2 * pr.nf], s));
       if (form == DSGRFT_FORM_F32)
         DS_TRY(launch_fine_f32(p, nu, u0, fl, 0, s));
+      else if (form == DSGRFT_FORM_F32_FFT)
+        DS_TRY(launch_fine_fft(p, nu, u0, fl, s));
       else
         DS_TRY(launch_fine_mfma(p, form, split, nu, u0, fl, s));
       if (tf) {
@@ -269,6 +274,8 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
       dalloc(&p->FBF16, f16b, tot) != hipSuccess ||
       dalloc(&p->F8, (size_t)4 * p->Cp * p->Mp, tot) != hipSuccess ||
       dalloc(&p->g_scale, (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
+      (fft_form_supported(M) &&
+       dalloc(&p->fft_tw, fft_table_elems(M, p->R, P) * sizeof(float2), tot) != hipSuccess) ||
       dalloc(&p->u_off, (size_t)bu * p->Mp * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->u_psi, (size_t)bu * p->Mp * sizeof(float2), tot) != hipSuccess ||
       dalloc((char **)&p->G, (size_t)bu * per_unit, tot) != hipSuccess ||
@@ -280,7 +287,9 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
     return DSGRFT_E_NOMEM;
   }
   p->ws_bytes = tot;
+  if (p->fft_tw) p->fft_chirp = p->fft_tw + M;
   if (launch_fine_tables(p, nullptr) != hipSuccess ||
+      (p->fft_tw && launch_fft_tables(p, nullptr) != hipSuccess) ||
       hipDeviceSynchronize() != hipSuccess) {
     release(p);
     return DSGRFT_E_DEVICE;
@@ -347,7 +356,7 @@ dsgrft_status dsgrft_search(dsgrft_plan p, dsgrft_form form, int32_t split,
                             int32_t *d_argf, void *stream) {
   if (!p || !d_echo || !d_pmax || !d_argf || n < 1) return DSGRFT_E_INVALID;
   if (!d_cells && (cc_begin < 0 || cc_begin + n > p->n_coarse)) return DSGRFT_E_INVALID;
-  dsgrft_status st = check_form(form, split);
+  dsgrft_status st = check_form(p, form, split);
   if (st != DSGRFT_OK) return st;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   return run_search(p, form, split, (const float2 *)d_echo, d_cells, cc_begin, n,
@@ -360,7 +369,7 @@ dsgrft_status dsgrft_search_full(dsgrft_plan p, dsgrft_form form, int32_t split,
   if (!p || !d_echo || !d_power || n < 1 || cc_begin < 0 || cc_begin + n > p->n_coarse)
     return DSGRFT_E_INVALID;
   if ((double)n * p->rows * (double)p->n_fine > 2147483647.0) return DSGRFT_E_INVALID;
-  dsgrft_status st = check_form(form, split);
+  dsgrft_status st = check_form(p, form, split);
   if (st != DSGRFT_OK) return st;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   return run_search(p, form, split, (const float2 *)d_echo, nullptr, cc_begin, n,

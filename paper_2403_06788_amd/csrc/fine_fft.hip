@@ -1,0 +1,274 @@
+// Stages a3 + a4, FFT form: the fine search of the GFT (eq. (44)) evaluated
+// the way Alg. 2 does it, with a slow-time FFT.
+//
+// With the coarse walk gathered and de-ramped (stages a1 + a2, FP32 layout
+// G[u][m][n]), the fine phase of orders 1 and 2 is
+//   exp(+j 2 pi (f1 m / M + f2 m^2 / M^2)),
+// so for each fine acceleration offset f2 the fine velocities f1 are bins of
+// one inverse DFT of the de-chirped row:
+//   Y[f1, f2][n] = sum_m (G[m][n] c_f2[m]) exp(+j 2 pi f1 m / M)
+//               = X_f2[f1 mod M],   c_f2[m] = exp(+j 2 pi f2 m^2 / M^2).
+// The wanted bins are the R fine velocities [-R/2, R - R/2) taken mod M
+// (when M < R several f1 share a bin and get identical values).  Order 3
+// sits in the gathered units as in the GEMM form.
+//
+// FFT of length M = A B (Cooley-Tukey, decimation in time): with
+// m = B m1 + m2 and output bin b = c + A d,
+//   X[c + A d] = sum_m2 W_B^(m2 d) [ W_M^(m2 c) sum_m1 W_A^(m1 c) x[B m1 + m2] ],
+// W_K = exp(+j 2 pi / K).  Pass 1: thread m2 holds x[B m1 + m2] for all m1 in
+// registers and runs an A-point FFT there, scales by the twiddles W_M^(m2 c)
+// and writes the A results to LDS; pass 2: thread c reads its B values and
+// runs a B-point FFT.  A workgroup owns NROW range rows of one unit; each
+// row's gathered samples stay in registers for all R chirps, and each thread
+// keeps its best (power, -fine) key, merged per row at the end with the same
+// 64-bit atomicMax as the GEMM form (ties to the smaller fine index).
+#include "internal.h"
+
+namespace {
+
+// exp(+j 2 pi k / 64) for k < 64, evaluated at compile time (Taylor series
+// of sin and cos on [-pi, pi], 24 terms: truncation far below double
+// rounding), so that twiddle factors of the unrolled FFTs fold into
+// instruction constants.
+struct Tw64 {
+  float re[64], im[64];
+};
+
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 24; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 24; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr Tw64 make_tw64() {
+  Tw64 t{};
+  for (int k = 0; k < 64; ++k) {
+    double a = 2.0 * kPi * k / 64.0;
+    if (a > kPi) a -= 2.0 * kPi;
+    t.re[k] = (float)taylor_cos(a);
+    t.im[k] = (float)taylor_sin(a);
+  }
+  return t;
+}
+
+__device__ constexpr Tw64 kTw = make_tw64();
+static_assert(make_tw64().re[0] == 1.0f && make_tw64().im[16] == 1.0f &&
+                  make_tw64().re[32] == -1.0f,
+              "twiddle table");
+
+__device__ inline float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__host__ __device__ constexpr int bitrev(int i, int n) {
+  int r = 0;
+  for (int s = 1; s < n; s <<= 1) {
+    r = (r << 1) | (i & 1);
+    i >>= 1;
+  }
+  return r;
+}
+
+// x * exp(+j 2 pi idx / 64), idx a compile-time constant after unrolling:
+// the factors 1, j, -j and exp(+-j pi/4), exp(+-j 3pi/4) take adds and one
+// multiply instead of a full complex product (IEEE rules keep the compiler
+// from dropping products by the zero parts itself).
+__device__ inline float2 twiddle(float2 x, int idx) {
+  constexpr float h = 0.70710678118654752f;  // sqrt(1/2)
+  switch (idx) {
+    case 0: return x;
+    case 16: return make_float2(-x.y, x.x);
+    case 48: return make_float2(x.y, -x.x);
+    case 8: return make_float2(h * (x.x - x.y), h * (x.x + x.y));
+    case 24: return make_float2(-h * (x.x + x.y), h * (x.x - x.y));
+    case 40: return make_float2(h * (x.y - x.x), -h * (x.x + x.y));
+    case 56: return make_float2(h * (x.x + x.y), h * (x.y - x.x));
+    default: return cmulf(x, make_float2(kTw.re[idx], kTw.im[idx]));
+  }
+}
+
+// In-register radix-2 FFT, N a power of two <= 64, positive exponent:
+// x[k] <- sum_j x[j] exp(+j 2 pi j k / N), natural order in and out.
+template <int N>
+__device__ inline void fft_reg(float2 (&x)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int j = bitrev(i, N);
+    if (j > i) {
+      const float2 t = x[i];
+      x[i] = x[j];
+      x[j] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= N; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < N; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; ++k) {
+        const float2 a = x[i + k];
+        const float2 b = twiddle(x[i + k + len / 2], k * (64 / len));
+        x[i + k] = make_float2(a.x + b.x, a.y + b.y);
+        x[i + k + len / 2] = make_float2(a.x - b.x, a.y - b.y);
+      }
+    }
+  }
+}
+
+__device__ inline unsigned long long umax64(unsigned long long a,
+                                            unsigned long long b) {
+  return a > b ? a : b;
+}
+
+__device__ inline unsigned long long shfl_xor64(unsigned long long v, int m) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  lo = __shfl_xor(lo, m);
+  hi = __shfl_xor(hi, m);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// G: gathered batch [nunits][Mp][rows_p] complex64; chirp [R2][M]; twM [M].
+// R2 = R for P >= 2 (f2 = i2 - R/2), 1 for P = 1.
+template <int A, int B>
+__global__ __launch_bounds__(256) void k_fine_fft(
+    const float2 *__restrict__ G, const float2 *__restrict__ chirp,
+    const float2 *__restrict__ twM, unsigned long long *__restrict__ packed,
+    float *__restrict__ full, int Mp, int rows, int rows_p, int R, int R2,
+    int64_t unit0, int R3, int C) {
+  constexpr int M = A * B;
+  constexpr int T = A > B ? A : B;  // threads per row
+  constexpr int NROW = 256 / T;
+  constexpr int ZS = A + 1;         // padded LDS row of pass-1 results
+  __shared__ float2 s_tw[M];
+  __shared__ float2 s_z[NROW * B * ZS];
+  const int tid = threadIdx.x;
+  const int rl = tid / T, q = tid % T;
+  const int bpu = rows_p / NROW;
+  const int64_t u = blockIdx.x / bpu;
+  const int n = (int)(blockIdx.x % bpu) * NROW + rl;
+  for (int i = tid; i < M; i += 256) s_tw[i] = twM[i];
+
+  float2 g[A];
+  if (q < B) {
+#pragma unroll
+    for (int m1 = 0; m1 < A; ++m1)
+      g[m1] = G[((int64_t)u * Mp + B * m1 + q) * rows_p + n];
+  }
+  __syncthreads();
+
+  const int64_t ug = unit0 + u;
+  const int64_t cpos = ug / R3;
+  const unsigned fbase = (unsigned)((ug % R3) * C);
+  const int h = R / 2;
+  unsigned long long best = 0ull;
+  float2 *zrow = s_z + rl * B * ZS;
+  for (int i2 = 0; i2 < R2; ++i2) {
+    if (q < B) {
+      const float2 *ch = chirp + (int64_t)i2 * M;
+      float2 x[A];
+#pragma unroll
+      for (int m1 = 0; m1 < A; ++m1) x[m1] = cmulf(g[m1], ch[B * m1 + q]);
+      fft_reg<A>(x);
+#pragma unroll
+      for (int c = 0; c < A; ++c) zrow[q * ZS + c] = cmulf(x[c], s_tw[(q * c) & (M - 1)]);
+    }
+    __syncthreads();
+    if (q < A) {
+      float2 y[B];
+#pragma unroll
+      for (int d = 0; d < B; ++d) y[d] = zrow[d * ZS + q];
+      fft_reg<B>(y);
+#pragma unroll
+      for (int d = 0; d < B; ++d) {
+        const int b = q + A * d;
+        const float pw = y[d].x * y[d].x + y[d].y * y[d].y;
+        // fine velocity indices u1 in [0, R) with (u1 - h) = b (mod M)
+        for (int u1 = (b + h) % M; u1 < R; u1 += M) {
+          const unsigned ff = fbase + (unsigned)(i2 * R + u1);
+          best = umax64(best, ((unsigned long long)__float_as_uint(pw) << 32) |
+                                  (0xffffffffu - ff));
+          if (full != nullptr && n < rows)
+            full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pw;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 1; s < T; s <<= 1) best = umax64(best, shfl_xor64(best, s));
+  if (q == 0 && n < rows) atomicMax(&packed[cpos * rows + n], best);
+}
+
+__global__ void k_fft_tables(int M, int R, int R2, int P, Lat L, float2 *twM,
+                             float2 *chirp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < M) {
+    double s, c;
+    sincospi(2.0 * (double)t / (double)M, &s, &c);
+    twM[t] = make_float2((float)c, (float)s);
+  }
+  if (t < (int64_t)R2 * M) {
+    const int i2 = (int)(t / M), m = (int)(t % M);
+    const int64_t f2 = (P >= 2) ? (int64_t)(i2 - R / 2) : 0;
+    chirp[t] = lat_phasor(L, lat_num(L, m, 0, f2, 0));
+  }
+}
+
+template <int A, int B>
+hipError_t launch_ab(dsgrft_plan p, int64_t nunits, int64_t unit0, float *full,
+                     hipStream_t s) {
+  constexpr int T = A > B ? A : B;
+  constexpr int NROW = 256 / T;
+  const int64_t blocks = nunits * (p->rows_p / NROW);
+  const int R2 = p->P >= 2 ? p->R : 1;
+  hipLaunchKernelGGL((k_fine_fft<A, B>), dim3((unsigned)blocks), dim3(256), 0, s,
+                     (const float2 *)p->G, p->fft_chirp, p->fft_tw,
+                     p->packed, full, p->Mp, p->rows, p->rows_p, p->R, R2, unit0,
+                     p->R3, p->C);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool fft_form_supported(int M) {
+  return M >= 64 && M <= 2048 && (M & (M - 1)) == 0;
+}
+
+size_t fft_table_elems(int M, int R, int P) {
+  return (size_t)M + (size_t)(P >= 2 ? R : 1) * M;
+}
+
+hipError_t launch_fft_tables(dsgrft_plan p, hipStream_t s) {
+  const int R2 = p->P >= 2 ? p->R : 1;
+  const int64_t n = (int64_t)R2 * p->M;
+  hipLaunchKernelGGL(k_fft_tables, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     p->M, p->R, R2, p->P, p->lat, p->fft_tw, p->fft_chirp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fine_fft(dsgrft_plan p, int64_t nunits, int64_t unit0,
+                           float *full, hipStream_t s) {
+  switch (p->M) {
+    case 64: return launch_ab<8, 8>(p, nunits, unit0, full, s);
+    case 128: return launch_ab<16, 8>(p, nunits, unit0, full, s);
+    case 256: return launch_ab<16, 16>(p, nunits, unit0, full, s);
+    case 512: return launch_ab<32, 16>(p, nunits, unit0, full, s);
+    case 1024: return launch_ab<32, 32>(p, nunits, unit0, full, s);
+    case 2048: return launch_ab<32, 64>(p, nunits, unit0, full, s);
+    default: return hipErrorInvalidValue;
+  }
+}

@@ -77,6 +77,8 @@ struct dsgrft_plan_s {
   float2 *u_psi;        // [batch_units][Mp] unit de-ramp phasors
   void *G;              // gathered batch, max 8 bytes per (unit,row,pulse)
   int32_t *g_scale;     // [batch_units][rows_p] per-row E8M0 codes (8-bit form)
+  float2 *fft_tw;       // [M] exp(+j 2 pi k / M) (FFT form; null if unsupported)
+  float2 *fft_chirp;    // [R or 1][M] fine-acceleration chirps (FFT form)
   unsigned long long *packed;  // [batch_cells][rows] (power bits, ~fine)
   void *det_ws;         // detection partials
   size_t det_ws_bytes;
@@ -145,6 +147,11 @@ hipError_t launch_fine_f32(dsgrft_plan p, int64_t nunits, int64_t unit0,
 hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
                             int64_t nunits, int64_t unit0, float *full,
                             hipStream_t s);
+bool fft_form_supported(int M);
+size_t fft_table_elems(int M, int R, int P);
+hipError_t launch_fft_tables(dsgrft_plan p, hipStream_t s);
+hipError_t launch_fine_fft(dsgrft_plan p, int64_t nunits, int64_t unit0,
+                           float *full, hipStream_t s);
 hipError_t launch_unpack(dsgrft_plan p, int64_t ncells, float *pmax,
                          int32_t *argf, hipStream_t s);
 hipError_t launch_grft(dsgrft_plan p, const float2 *echo, int64_t cc_begin,

@@ -153,3 +153,18 @@ def test_config5_jerk_search_subset():
             at32 = P[np.searchsorted(probe, af32[ci, r])]
             assert abs(at32 - pm32[ci, r]) <= 1e-5 * scale
             assert P.max() <= pm32[ci, r] + 2e-5 * scale
+
+
+def test_config3_fft_form_sampled():
+    """FFT fine-velocity form at M = 1024: sampled rows of 3 cells against the
+    oracle within the FP32 tolerance, and against the GEMM FP32 form."""
+    case, plan, grid, echo = _setup(3)
+    cells = torch.tensor([0, 1234, plan.n_coarse - 1], dtype=torch.int64)
+    pm, af = plan.search(echo, "f32fft", 1, cells=cells)
+    pm32, af32 = plan.search(echo, "f32", 1, cells=cells)
+    pm, af, pm32 = pm.cpu().numpy(), af.cpu().numpy(), pm32.cpu().numpy()
+    rows = sorted(np.random.default_rng(9).choice(plan.rows, 24, replace=False).tolist())
+    idx = {int(c): i for i, c in enumerate(cells.tolist())}
+    _check_rows({c: pm[i] for c, i in idx.items()}, {c: af[i] for c, i in idx.items()},
+                case["echo"], grid, list(idx), rows, 1e-5)
+    assert np.abs(pm - pm32).max() <= 2e-5 * pm32.max()
