@@ -24,6 +24,8 @@ Modules
             (independent of the integer numerator formula) for tiny inputs.
   lowp      float64 model of the 8-bit float (OCP E4M3) form of the fine
             search: operand rounding, power-of-two scales, split products.
+  fd        frequency-domain mGIFT (Alg. 1): range spectrum, coarse RM phase
+            ramp, IFFT, pre-DFM phase; DS-GRFT on top of it.
 
 Parity status: every function here is pinned by a CPU test (brute force,
 closed forms, invariants, or a library routine); see tests/test_oracle_*.py.
