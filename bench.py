@@ -48,11 +48,20 @@ def recorded_traffic(form, split):
     return d.get("bytes_per_launch")
 
 
-def oracle_rows(echo, grid, cells, rows):
-    """Oracle reduced values for sampled (cell, rows): list of (P_row [R^P])."""
+def oracle_rows(echo, grid, cells, rows, mgift="td"):
+    """Oracle power rows for sampled (cell, rows): {cell: P [rows, n_fine]}."""
     import numpy as np
+    from oracle import fd as OF
     from oracle import transforms as OT
     out = {}
+    if mgift == "fd":
+        Np = OF.pad_length(grid)
+        S = OF.range_spectrum(echo, Np)
+        F = OT.fine_matrix(grid)
+        r = np.asarray(rows) - grid.n_begin
+        for k in cells:
+            out[int(k)] = np.abs(OF.mgift_fd(echo, grid, int(k), Np, S)[:, r].T @ F) ** 2
+        return out
     for k in cells:
         y = OT.dsgrft_cell(echo, grid, int(k), rows=rows)
         out[int(k)] = np.abs(y) ** 2
@@ -86,6 +95,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", default="f16")
+    ap.add_argument("--mgift", default="td", choices=("td", "fd"),
+                    help="coarse compensation: time-domain gather or frequency domain")
     ap.add_argument("--split", type=int, default=1)
     ap.add_argument("--f32-cells", type=int, default=48)
     ap.add_argument("--no-sweep", action="store_true")
@@ -118,7 +129,7 @@ def main():
     c = synth.CONFIGS[3]
     r = c["radar"]
     echo_np = case["echo"]
-    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"])
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"], mgift=args.mgift)
     echo = torch.from_numpy(echo_np).cuda()
     cells = plan.n_coarse
     cp_total = float(cells) * plan.rows * plan.n_fine * plan.M
@@ -191,7 +202,7 @@ def main():
     s_cells = sorted(set([bk, 0, 1] + [int(x) for x in rng.choice(cells, 5, replace=False)]))
     s_rows = sorted(set([brow] + [int(x) for x in rng.choice(plan.rows, 40, replace=False)]))
     t = time.perf_counter()
-    ref = oracle_rows(echo_np, grid, s_cells, s_rows)
+    ref = oracle_rows(echo_np, grid, s_cells, s_rows, args.mgift)
     log(f"oracle rows: {len(s_cells)} cells x {len(s_rows)} rows in {time.perf_counter() - t:.1f} s")
     forms = {}
     err, bad, clear, scale = sampled_error(pm_main, af_main, ref, s_rows, 1e-3)
@@ -267,6 +278,8 @@ def main():
                                "P=2 (v +-600 m/s, a +-50 m/s^2), 2460 coarse x 10^4 fine "
                                "cells, 8 targets at -20 dB, fc=1 GHz, fs=10 MHz, PRF=500 Hz",
                    "form": f"{args.form} MFMA, split {args.split}, FP32 accumulation",
+                   "mgift": "time-domain nearest-bin gather" if args.mgift == "td"
+                            else "frequency-domain coarse compensation (Alg. 1)",
                    "cells": cells * plan.rows * plan.n_fine, "pulses": plan.M},
         "roofline": roofline,
         "gather_roofline": gather,

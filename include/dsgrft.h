@@ -97,6 +97,12 @@ typedef struct {
   int32_t n_end;      /*   interest, Sec. IV-E); 0,0 means [0, N)         */
   dsgrft_axis axis[3];/* extents of v, a, j (orders above P are ignored)  */
   int32_t batch;      /* gathered units per fine-search batch; 0 = auto   */
+  int32_t mgift;      /* coarse compensation (mGIFT, Alg. 1):             */
+                      /*   0: time domain, nearest range bin of the walk  */
+                      /*   1: frequency domain, exp(+j 2 pi k_s x / N') on */
+                      /*      the range spectrum zero-padded to N' (the   */
+                      /*      smallest power of two >= N + walk bound),   */
+                      /*      then IFFT; N' <= 16384 else E_UNSUPPORTED   */
 } dsgrft_config;
 
 typedef struct {
@@ -146,14 +152,19 @@ const char *dsgrft_status_string(dsgrft_status s);
  * [cc_begin, cc_begin + n): d_off[i][m] = round-half-up walk in bins of the
  * cell centre (mGIFT envelope correction, eq. (46)), d_psi[i][m] =
  * exp(+j 2 pi Num/M^3), the pre-DFM phase H_pre-DFM of eq. (47), complex64.
- * Layout [n][M].  E_INVALID if the range leaves [0, n_coarse). */
+ * Layout [n][M].  The offsets are the nearest-bin walk whatever the plan's
+ * mgift mode.  E_INVALID if the range leaves [0, n_coarse). */
 dsgrft_status dsgrft_coarse_tables(dsgrft_plan plan, int64_t cc_begin,
                                    int64_t n, int32_t *d_off, void *d_psi,
                                    void *stream);
 
-/* mGIFT in the time domain (stages a1 + a2, Alg. 1): for coarse cells
- * [cc_begin, cc_begin + n) writes y[i][m][r] = S(m, n_begin + r + off) * psi
- * (S = 0 outside [0, N)) as complex64, layout [n][M][rows]. */
+/* mGIFT (stages a1 + a2, Alg. 1): for coarse cells [cc_begin, cc_begin + n)
+ * writes y[i][m][r] as complex64, layout [n][M][rows].  Time-domain plans
+ * (mgift = 0): y = S(m, n_begin + r + off) * psi (S = 0 outside [0, N)).
+ * Frequency-domain plans (mgift = 1): y = psi * (1/N') sum_k S'[m][k]
+ * exp(+j 2 pi k_s x(m) / N') exp(+j 2 pi k (n_begin + r) / N'), with S' the
+ * range DFT of row m zero-padded to N', k_s the signed frequency index and
+ * x(m) = Num(m) / (R M^3) the cell's walk in bins (H_RM of eq. (10)). */
 dsgrft_status dsgrft_mgift(dsgrft_plan plan, const void *d_echo,
                            int64_t cc_begin, int64_t n, void *d_out,
                            void *stream);

@@ -39,7 +39,7 @@ class Axis(C.Structure):
 class Config(C.Structure):
     _fields_ = [("M", C.c_int32), ("N", C.c_int32), ("order", C.c_int32),
                 ("n_begin", C.c_int32), ("n_end", C.c_int32),
-                ("axis", Axis * 3), ("batch", C.c_int32)]
+                ("axis", Axis * 3), ("batch", C.c_int32), ("mgift", C.c_int32)]
 
 
 class PlanInfo(C.Structure):

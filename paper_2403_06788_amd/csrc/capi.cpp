@@ -44,7 +44,8 @@ hipError_t dalloc(T **p, size_t bytes, size_t &total) {
 void release(dsgrft_plan p) {
   if (!p) return;
   void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->u_off, p->u_psi,
-                  p->G, p->g_scale, p->fft_tw, p->packed, p->det_ws, p->adj_ws};
+                  p->G, p->g_scale, p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
+                  p->packed, p->det_ws, p->adj_ws};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -86,6 +87,8 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
                          int64_t cc_begin, int64_t n, float *pmax, int32_t *argf,
                          float *full, hipStream_t s) {
   const int64_t Bc = p->batch_cells, Bu = p->batch_units;
+  if (p->fd) DS_TRY(launch_range_fft(p, echo, s));
+  const GatherSrc src = gather_src(p, echo);
   for (int64_t c0 = 0; c0 < n; c0 += Bc) {
     const int64_t nc = (n - c0) < Bc ? (n - c0) : Bc;
     DS_TRY(launch_fill_u64(p->packed, nc * p->rows, s));
@@ -95,15 +98,16 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
     for (int64_t u0 = 0; u0 < nut; u0 += Bu) {
       const int64_t nu = (nut - u0) < Bu ? (nut - u0) : Bu;
       DS_TRY(launch_unit_tables(p, cl, cc_begin + c0, u0, nu, s));
+      if (p->fd) DS_TRY(launch_fd_shift(p, cl, cc_begin + c0, u0, nu, p->R3, s));
       auto &pr = p->prof;
       const bool tg = pr.ng < pr.cap, tf = pr.nf < pr.cap;
       const double samples = (double)nu * p->rows * p->M;
       const double bg = gather_bytes(form, split);
       if (tg) DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng], s));
       if (form == DSGRFT_FORM_F32 || form == DSGRFT_FORM_F32_FFT)
-        DS_TRY(launch_gather_f32(p, echo, nu, s));
+        DS_TRY(launch_gather_f32(p, src, nu, s));
       else
-        DS_TRY(launch_gather_lp(p, form, split, echo, nu, s));
+        DS_TRY(launch_gather_lp(p, form, split, src, nu, s));
       if (tg) {
         DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng + 1], s));
         pr.ng++;
@@ -131,6 +135,29 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
 
 }  // namespace
 
+// Zero-padded range-FFT length of the frequency-domain mGIFT: the smallest
+// power of two >= N + W, W = ceil(sum_p max|i_c,p| (M-1)^p M^(3-p) / (R M^3))
+// + 1 bounds every coarse walk in bins.
+int fd_pad_length(dsgrft_plan p) {
+  const __int128 M = p->M;
+  __int128 tot = 0;
+  for (int q = 0; q < p->P; ++q) {
+    const long long lo = (long long)p->ilo[q] + p->h;
+    const long long hi = (long long)p->ilo[q] + (long long)(p->K[q] - 1) * p->R + p->h;
+    const long long mag = (lo < 0 ? -lo : lo) > (hi < 0 ? -hi : hi) ? (lo < 0 ? -lo : lo)
+                                                                     : (hi < 0 ? -hi : hi);
+    __int128 t = mag;
+    for (int e = 0; e <= q; ++e) t *= (M - 1);
+    for (int e = 0; e < 2 - q; ++e) t *= M;
+    tot += t;
+  }
+  const __int128 den = (__int128)p->R * M * M * M;
+  const long long W = (long long)((tot + den - 1) / den) + 1;
+  long long need = (long long)p->N + W, L = 1;
+  while (L < need && L <= (1LL << 40)) L *= 2;
+  return L > (1LL << 30) ? (1 << 30) : (int)L;
+}
+
 extern "C" {
 
 const char *dsgrft_status_string(dsgrft_status s) {
@@ -156,6 +183,7 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   if (radar->kappa != 1.0) return DSGRFT_E_UNSUPPORTED;
   const int M = cfg->M, N = cfg->N, P = cfg->order;
   if (M < 1 || N < 1 || P < 1 || P > 3 || cfg->batch < 0) return DSGRFT_E_INVALID;
+  if (cfg->mgift != 0 && cfg->mgift != 1) return DSGRFT_E_INVALID;
   if (M > (1 << 20) || N > (1 << 28)) return DSGRFT_E_INVALID;
   int nb = cfg->n_begin, ne = cfg->n_end;
   if (nb == 0 && ne == 0) ne = N;
@@ -259,6 +287,14 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
     p->batch_cells = bu;
   }
   p->batch_units = bu;
+  p->fd = cfg->mgift;
+  if (p->fd) {
+    p->fd_np = fd_pad_length(p);
+    if (p->fd_np > 16384) {
+      delete p;
+      return DSGRFT_E_UNSUPPORTED;
+    }
+  }
 
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
@@ -276,6 +312,10 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
       dalloc(&p->g_scale, (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
       (fft_form_supported(M) &&
        dalloc(&p->fft_tw, fft_table_elems(M, p->R, P) * sizeof(float2), tot) != hipSuccess) ||
+      (p->fd &&
+       (dalloc(&p->fd_tw, (size_t)p->fd_np * sizeof(float2), tot) != hipSuccess ||
+        dalloc(&p->fd_spec, (size_t)M * p->fd_np * sizeof(float2), tot) != hipSuccess ||
+        dalloc(&p->fd_E, (size_t)bu * M * p->rows_p * sizeof(float2), tot) != hipSuccess)) ||
       dalloc(&p->u_off, (size_t)bu * p->Mp * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->u_psi, (size_t)bu * p->Mp * sizeof(float2), tot) != hipSuccess ||
       dalloc((char **)&p->G, (size_t)bu * per_unit, tot) != hipSuccess ||
@@ -290,6 +330,7 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   if (p->fft_tw) p->fft_chirp = p->fft_tw + M;
   if (launch_fine_tables(p, nullptr) != hipSuccess ||
       (p->fft_tw && launch_fft_tables(p, nullptr) != hipSuccess) ||
+      (p->fd && launch_fd_twiddles(p, nullptr) != hipSuccess) ||
       hipDeviceSynchronize() != hipSuccess) {
     release(p);
     return DSGRFT_E_DEVICE;
@@ -341,10 +382,14 @@ dsgrft_status dsgrft_mgift(dsgrft_plan p, const void *d_echo, int64_t cc_begin,
     return DSGRFT_E_INVALID;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
+  if (p->fd) DS_TRY(launch_range_fft(p, (const float2 *)d_echo, s));
+  const GatherSrc src = gather_src(p, (const float2 *)d_echo);
   for (int64_t c0 = 0; c0 < n; c0 += p->batch_units) {
     const int64_t nc = (n - c0) < p->batch_units ? (n - c0) : p->batch_units;
-    DS_TRY(launch_coarse_tables(p, cc_begin + c0, nc, p->Mp, p->u_off, p->u_psi, s));
-    DS_TRY(launch_mgift_out(p, (const float2 *)d_echo, nc,
+    DS_TRY(launch_coarse_tables(p, cc_begin + c0, nc, p->Mp, p->u_off, p->u_psi, s,
+                                p->fd != 0));
+    if (p->fd) DS_TRY(launch_fd_shift(p, nullptr, cc_begin + c0, 0, nc, 1, s));
+    DS_TRY(launch_mgift_out(p, src, nc,
                             (float2 *)d_out + c0 * (int64_t)p->M * p->rows, s));
   }
   return DSGRFT_OK;

@@ -22,112 +22,13 @@
 // row's gathered samples stay in registers for all R chirps, and each thread
 // keeps its best (power, -fine) key, merged per row at the end with the same
 // 64-bit atomicMax as the GEMM form (ties to the smaller fine index).
+#include "fft_reg.h"
 #include "internal.h"
 
 namespace {
 
-// exp(+j 2 pi k / 64) for k < 64, evaluated at compile time (Taylor series
-// of sin and cos on [-pi, pi], 24 terms: truncation far below double
-// rounding), so that twiddle factors of the unrolled FFTs fold into
-// instruction constants.
-struct Tw64 {
-  float re[64], im[64];
-};
-
-constexpr double kPi = 3.14159265358979323846;
-
-constexpr double taylor_sin(double x) {
-  double term = x, sum = x;
-  for (int k = 1; k < 24; ++k) {
-    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
-    sum += term;
-  }
-  return sum;
-}
-
-constexpr double taylor_cos(double x) {
-  double term = 1.0, sum = 1.0;
-  for (int k = 1; k < 24; ++k) {
-    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
-    sum += term;
-  }
-  return sum;
-}
-
-constexpr Tw64 make_tw64() {
-  Tw64 t{};
-  for (int k = 0; k < 64; ++k) {
-    double a = 2.0 * kPi * k / 64.0;
-    if (a > kPi) a -= 2.0 * kPi;
-    t.re[k] = (float)taylor_cos(a);
-    t.im[k] = (float)taylor_sin(a);
-  }
-  return t;
-}
-
-__device__ constexpr Tw64 kTw = make_tw64();
-static_assert(make_tw64().re[0] == 1.0f && make_tw64().im[16] == 1.0f &&
-                  make_tw64().re[32] == -1.0f,
-              "twiddle table");
-
-__device__ inline float2 cmulf(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-__host__ __device__ constexpr int bitrev(int i, int n) {
-  int r = 0;
-  for (int s = 1; s < n; s <<= 1) {
-    r = (r << 1) | (i & 1);
-    i >>= 1;
-  }
-  return r;
-}
-
-// x * exp(+j 2 pi idx / 64), idx a compile-time constant after unrolling:
-// the factors 1, j, -j and exp(+-j pi/4), exp(+-j 3pi/4) take adds and one
-// multiply instead of a full complex product (IEEE rules keep the compiler
-// from dropping products by the zero parts itself).
-__device__ inline float2 twiddle(float2 x, int idx) {
-  constexpr float h = 0.70710678118654752f;  // sqrt(1/2)
-  switch (idx) {
-    case 0: return x;
-    case 16: return make_float2(-x.y, x.x);
-    case 48: return make_float2(x.y, -x.x);
-    case 8: return make_float2(h * (x.x - x.y), h * (x.x + x.y));
-    case 24: return make_float2(-h * (x.x + x.y), h * (x.x - x.y));
-    case 40: return make_float2(h * (x.y - x.x), -h * (x.x + x.y));
-    case 56: return make_float2(h * (x.x + x.y), h * (x.y - x.x));
-    default: return cmulf(x, make_float2(kTw.re[idx], kTw.im[idx]));
-  }
-}
-
-// In-register radix-2 FFT, N a power of two <= 64, positive exponent:
-// x[k] <- sum_j x[j] exp(+j 2 pi j k / N), natural order in and out.
-template <int N>
-__device__ inline void fft_reg(float2 (&x)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    const int j = bitrev(i, N);
-    if (j > i) {
-      const float2 t = x[i];
-      x[i] = x[j];
-      x[j] = t;
-    }
-  }
-#pragma unroll
-  for (int len = 2; len <= N; len <<= 1) {
-#pragma unroll
-    for (int i = 0; i < N; i += len) {
-#pragma unroll
-      for (int k = 0; k < len / 2; ++k) {
-        const float2 a = x[i + k];
-        const float2 b = twiddle(x[i + k + len / 2], k * (64 / len));
-        x[i + k] = make_float2(a.x + b.x, a.y + b.y);
-        x[i + k + len / 2] = make_float2(a.x - b.x, a.y - b.y);
-      }
-    }
-  }
-}
+using fftreg::cmulf;
+using fftreg::fft_reg;
 
 __device__ inline unsigned long long umax64(unsigned long long a,
                                             unsigned long long b) {

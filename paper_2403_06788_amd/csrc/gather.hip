@@ -39,7 +39,8 @@ __global__ void k_gather_f32(const float2 *__restrict__ echo,
                              const int32_t *__restrict__ off,
                              const float2 *__restrict__ psi, int M, int N,
                              int Mp, int rows, int rows_p, int n_begin,
-                             int64_t nunits, float2 *__restrict__ G) {
+                             int64_t estride, int64_t nunits,
+                             float2 *__restrict__ G) {
   const int rb = (rows_p + 255) / 256;
   const int64_t um = (int64_t)blockIdx.x / rb;  // u * Mp + m
   const int r = (int)(blockIdx.x % rb) * 256 + threadIdx.x;
@@ -48,7 +49,7 @@ __global__ void k_gather_f32(const float2 *__restrict__ echo,
   float2 v = make_float2(0.f, 0.f);
   if (m < M && r < rows) {
     int idx = n_begin + r + off[um];
-    v = cmul(sample(echo, N, m, idx), psi[um]);
+    v = cmul(sample(echo + (um / Mp) * estride, N, m, idx), psi[um]);
   }
   G[um * rows_p + r] = v;
 }
@@ -56,7 +57,8 @@ __global__ void k_gather_f32(const float2 *__restrict__ echo,
 __global__ void k_mgift_out(const float2 *__restrict__ echo,
                             const int32_t *__restrict__ off,
                             const float2 *__restrict__ psi, int M, int N, int Mp,
-                            int rows, int n_begin, float2 *__restrict__ out) {
+                            int rows, int n_begin, int64_t estride,
+                            float2 *__restrict__ out) {
   const int rb = (rows + 255) / 256;
   const int64_t um0 = (int64_t)blockIdx.x / rb;  // u * M + m
   const int r = (int)(blockIdx.x % rb) * 256 + threadIdx.x;
@@ -65,7 +67,7 @@ __global__ void k_mgift_out(const float2 *__restrict__ echo,
   if (r >= rows) return;
   int64_t um = u * Mp + m;
   int idx = n_begin + r + off[um];
-  out[((int64_t)u * M + m) * rows + r] = cmul(sample(echo, N, m, idx), psi[um]);
+  out[((int64_t)u * M + m) * rows + r] = cmul(sample(echo + u * estride, N, m, idx), psi[um]);
 }
 
 template <typename T>
@@ -77,7 +79,7 @@ template <typename T, int NP>
 __global__ __launch_bounds__(256) void k_gather_lp(
     const float2 *__restrict__ echo, const int32_t *__restrict__ off,
     const float2 *__restrict__ psi, int M, int N, int Mp, int rows, int n_begin,
-    int NB, int KB, int64_t nunits, uint4 *__restrict__ G) {
+    int64_t estride, int NB, int KB, int64_t nunits, uint4 *__restrict__ G) {
   const int lane = threadIdx.x & 63;
   const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= nunits * NB * KB) return;
@@ -86,6 +88,7 @@ __global__ __launch_bounds__(256) void k_gather_lp(
   const int64_t u = w / ((int64_t)KB * NB);
   const int r = nb * 32 + (lane & 31);
   const int m0 = kb * 16 + 8 * (lane >> 5);
+  echo += u * estride;
   uint16_t re_h[8], im_h[8], re_l[8], im_l[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -141,7 +144,7 @@ template <int NP, bool STAGED>
 __global__ __launch_bounds__(256) void k_gather_f8(
     const float2 *__restrict__ echo, const int32_t *__restrict__ off,
     const float2 *__restrict__ psi, int M, int N, int Mp, int rows, int rows_p,
-    int n_begin, int NB, int KB8, uint4 *__restrict__ G,
+    int n_begin, int64_t estride, int NB, int KB8, uint4 *__restrict__ G,
     int32_t *__restrict__ scale) {
   extern __shared__ char smem[];
   float2 *s_psi = (float2 *)smem;              // [Mp]
@@ -151,6 +154,7 @@ __global__ __launch_bounds__(256) void k_gather_f8(
   const int nb = (int)(blockIdx.x % NB);
   const int64_t u = blockIdx.x / NB;
   const int t = threadIdx.x;
+  echo += u * estride;
   const int32_t *uo = off + u * Mp;
   const float2 *up = psi + u * Mp;
   if (STAGED) {
@@ -243,25 +247,30 @@ __global__ __launch_bounds__(256) void k_gather_f8(
 
 }  // namespace
 
-hipError_t launch_gather_f32(dsgrft_plan p, const float2 *echo, int64_t nunits,
+GatherSrc gather_src(dsgrft_plan p, const float2 *echo) {
+  if (p->fd) return GatherSrc{p->fd_E, p->rows_p, 0, (int64_t)p->M * p->rows_p};
+  return GatherSrc{echo, p->N, p->n_begin, 0};
+}
+
+hipError_t launch_gather_f32(dsgrft_plan p, GatherSrc src, int64_t nunits,
                              hipStream_t s) {
   dim3 grid((unsigned)(((p->rows_p + 255) / 256) * nunits * p->Mp));
-  hipLaunchKernelGGL(k_gather_f32, grid, dim3(256), 0, s, echo, p->u_off, p->u_psi,
-                     p->M, p->N, p->Mp, p->rows, p->rows_p, p->n_begin, nunits,
-                     (float2 *)p->G);
+  hipLaunchKernelGGL(k_gather_f32, grid, dim3(256), 0, s, src.echo, p->u_off, p->u_psi,
+                     p->M, src.N, p->Mp, p->rows, p->rows_p, src.n_begin,
+                     src.unit_stride, nunits, (float2 *)p->G);
   return hipGetLastError();
 }
 
-hipError_t launch_mgift_out(dsgrft_plan p, const float2 *echo, int64_t nunits,
+hipError_t launch_mgift_out(dsgrft_plan p, GatherSrc src, int64_t nunits,
                             float2 *out, hipStream_t s) {
   dim3 grid((unsigned)(((p->rows + 255) / 256) * nunits * p->M));
-  hipLaunchKernelGGL(k_mgift_out, grid, dim3(256), 0, s, echo, p->u_off, p->u_psi,
-                     p->M, p->N, p->Mp, p->rows, p->n_begin, out);
+  hipLaunchKernelGGL(k_mgift_out, grid, dim3(256), 0, s, src.echo, p->u_off, p->u_psi,
+                     p->M, src.N, p->Mp, p->rows, src.n_begin, src.unit_stride, out);
   return hipGetLastError();
 }
 
 hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
-                            const float2 *echo, int64_t nunits, hipStream_t s) {
+                            GatherSrc src, int64_t nunits, hipStream_t s) {
   // G's lo planes enter from split 3 on (split 2 adds the fine table's lo)
   const bool lo = split >= 3;
   uint4 *G = (uint4 *)p->G;
@@ -269,10 +278,10 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
     dim3 grid((unsigned)(nunits * p->NB));
     const size_t lds = (size_t)p->Mp * (sizeof(float2) + sizeof(int32_t));
     const bool staged = lds <= 48 * 1024;
-#define DS_GATHER_F8(NP, ST)                                                        \
-  hipLaunchKernelGGL((k_gather_f8<NP, ST>), grid, dim3(256), ST ? lds : 0, s, echo,  \
-                     p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows, p->rows_p,     \
-                     p->n_begin, p->NB, p->KB / 4, G, p->g_scale)
+#define DS_GATHER_F8(NP, ST)                                                          \
+  hipLaunchKernelGGL((k_gather_f8<NP, ST>), grid, dim3(256), ST ? lds : 0, s, src.echo, \
+                     p->u_off, p->u_psi, p->M, src.N, p->Mp, p->rows, p->rows_p,       \
+                     src.n_begin, src.unit_stride, p->NB, p->KB / 4, G, p->g_scale)
     if (lo) {
       if (staged) DS_GATHER_F8(4, true); else DS_GATHER_F8(4, false);
     } else {
@@ -283,26 +292,17 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
   }
   int64_t waves = nunits * p->NB * p->KB;
   dim3 grid((unsigned)((waves + 3) / 4));
+#define DS_GATHER_LP(T, NP)                                                           \
+  hipLaunchKernelGGL((k_gather_lp<T, NP>), grid, dim3(256), 0, s, src.echo, p->u_off,   \
+                     p->u_psi, p->M, src.N, p->Mp, p->rows, src.n_begin,                \
+                     src.unit_stride, p->NB, p->KB, nunits, G)
   if (form == DSGRFT_FORM_F16) {
-    if (!lo)
-      hipLaunchKernelGGL((k_gather_lp<_Float16, 2>), grid, dim3(256), 0, s, echo,
-                         p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows,
-                         p->n_begin, p->NB, p->KB, nunits, G);
-    else
-      hipLaunchKernelGGL((k_gather_lp<_Float16, 4>), grid, dim3(256), 0, s, echo,
-                         p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows,
-                         p->n_begin, p->NB, p->KB, nunits, G);
+    if (!lo) DS_GATHER_LP(_Float16, 2); else DS_GATHER_LP(_Float16, 4);
   } else if (form == DSGRFT_FORM_BF16) {
-    if (!lo)
-      hipLaunchKernelGGL((k_gather_lp<__bf16, 2>), grid, dim3(256), 0, s, echo,
-                         p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows,
-                         p->n_begin, p->NB, p->KB, nunits, G);
-    else
-      hipLaunchKernelGGL((k_gather_lp<__bf16, 4>), grid, dim3(256), 0, s, echo,
-                         p->u_off, p->u_psi, p->M, p->N, p->Mp, p->rows,
-                         p->n_begin, p->NB, p->KB, nunits, G);
+    if (!lo) DS_GATHER_LP(__bf16, 2); else DS_GATHER_LP(__bf16, 4);
   } else {
     return hipErrorInvalidValue;
   }
+#undef DS_GATHER_LP
   return hipGetLastError();
 }

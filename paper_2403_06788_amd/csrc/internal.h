@@ -79,6 +79,12 @@ struct dsgrft_plan_s {
   int32_t *g_scale;     // [batch_units][rows_p] per-row E8M0 codes (8-bit form)
   float2 *fft_tw;       // [M] exp(+j 2 pi k / M) (FFT form; null if unsupported)
   float2 *fft_chirp;    // [R or 1][M] fine-acceleration chirps (FFT form)
+  // frequency-domain mGIFT (cfg.mgift == 1)
+  int fd;               // 1: frequency-domain coarse compensation
+  int fd_np;            // padded range-FFT length
+  float2 *fd_tw;        // [fd_np] exp(+j 2 pi k / fd_np)
+  float2 *fd_spec;      // [M][fd_np] range spectrum of the current echo
+  float2 *fd_E;         // [batch_units][M][rows_p] shifted rows
   unsigned long long *packed;  // [batch_cells][rows] (power bits, ~fine)
   void *det_ws;         // detection partials
   size_t det_ws_bytes;
@@ -133,14 +139,27 @@ hipError_t launch_unit_tables(dsgrft_plan p, const int64_t *cells,
                               hipStream_t s);
 hipError_t launch_coarse_tables(dsgrft_plan p, int64_t cc_begin, int64_t n,
                                 int stride, int32_t *off, float2 *psi,
-                                hipStream_t s);
+                                hipStream_t s, bool zero_off = false);
 size_t detect_ws_bytes(int64_t max_entries);
-hipError_t launch_gather_f32(dsgrft_plan p, const float2 *echo, int64_t nunits,
+// Where the gathers read: the echo ([M][N], window from n_begin) or, in the
+// frequency-domain mode, the shifted rows of each unit ([u][M][rows_p]).
+struct GatherSrc {
+  const float2 *echo;
+  int N, n_begin;
+  int64_t unit_stride;
+};
+GatherSrc gather_src(dsgrft_plan p, const float2 *echo);
+hipError_t launch_gather_f32(dsgrft_plan p, GatherSrc src, int64_t nunits,
                              hipStream_t s);
 hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
-                            const float2 *echo, int64_t nunits, hipStream_t s);
-hipError_t launch_mgift_out(dsgrft_plan p, const float2 *echo, int64_t nunits,
+                            GatherSrc src, int64_t nunits, hipStream_t s);
+hipError_t launch_mgift_out(dsgrft_plan p, GatherSrc src, int64_t nunits,
                             float2 *out, hipStream_t s);
+int fd_pad_length(dsgrft_plan p);
+hipError_t launch_fd_twiddles(dsgrft_plan p, hipStream_t s);
+hipError_t launch_range_fft(dsgrft_plan p, const float2 *echo, hipStream_t s);
+hipError_t launch_fd_shift(dsgrft_plan p, const int64_t *cells, int64_t cc_base,
+                           int64_t unit0, int64_t nunits, int R3, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *ptr, int64_t n, hipStream_t s);
 hipError_t launch_fine_f32(dsgrft_plan p, int64_t nunits, int64_t unit0,
                            float *full, int64_t full_cell0, hipStream_t s);

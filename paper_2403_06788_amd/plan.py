@@ -36,11 +36,13 @@ class Plan:
 
     fc, fs, prf: carrier [Hz], range sampling rate [Hz], PRF [Hz];
     axes: [(vmin, vmax), (amin, amax), (jmin, jmax)][:order];
-    rows: optional (n_begin, n_end) range rows of interest.
+    rows: optional (n_begin, n_end) range rows of interest;
+    mgift: "td" (nearest-bin gather along the coarse walk) or "fd"
+    (frequency-domain coarse compensation of Alg. 1).
     """
 
     def __init__(self, fc, fs, prf, M, N, order, axes, rows=None, c=3.0e8,
-                 kappa=1.0, batch=0):
+                 kappa=1.0, batch=0, mgift="td"):
         L = _lib.lib()
         radar = _lib.Radar(fc, fs, prf, c, kappa)
         cfg = _lib.Config()
@@ -49,6 +51,9 @@ class Plan:
         for p, ax in enumerate(axes):
             cfg.axis[p].min, cfg.axis[p].max = float(ax[0]), float(ax[1])
         cfg.batch = batch
+        if mgift not in ("td", "fd"):
+            raise ValueError('mgift must be "td" or "fd"')
+        cfg.mgift = 1 if mgift == "fd" else 0
         h = C.c_void_p()
         check("dsgrft_plan_create", L.dsgrft_plan_create(C.byref(radar), C.byref(cfg), C.byref(h)))
         self._h = h
@@ -67,6 +72,7 @@ class Plan:
         self.step = tuple(info.step)
         self.workspace_bytes = info.workspace_bytes
         self.prf = prf
+        self.mgift_mode = mgift
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,100 @@
+"""Frequency-domain mGIFT (Alg. 1) through the C ABI against the FP64 oracle:
+the compensated rows themselves, the full map (FP32), every fine-search form
+on top of it, and the time-domain path where the coarse walk is an integer."""
+import numpy as np
+import pytest
+import torch
+
+from cases import CASES, make_case, near_tie_check, plan_for
+from oracle import fd as OF
+from oracle import transforms as OT
+from oracle.grid import Axis, Radar, make_grid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def fcase(request):
+    c = make_case(request.param)
+    c["name"] = request.param
+    c["plan"] = plan_for(c, mgift="fd")
+    c["echo_dev"] = torch.from_numpy(c["echo"]).cuda()
+    c["P_fd"] = OF.dsgrft_fd_power(c["echo"], c["grid"])
+    return c
+
+
+def test_fd_mgift_rows_match_oracle(fcase):
+    g = fcase["grid"]
+    y = fcase["plan"].mgift(fcase["echo_dev"]).cpu().numpy()
+    Np = OF.pad_length(g)
+    S = OF.range_spectrum(fcase["echo"], Np)
+    ref = np.stack([OF.mgift_fd(fcase["echo"], g, k, Np, S) for k in range(g.n_coarse)])
+    assert np.abs(y - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_fd_full_map_fp32_matches_oracle(fcase):
+    P = fcase["plan"].search_full(fcase["echo_dev"], "f32", 1).cpu().numpy().astype(np.float64)
+    ref = fcase["P_fd"]
+    assert np.abs(P - ref).max() / ref.max() <= 1e-5
+
+
+@pytest.mark.parametrize("form,split,tol", [("f32", 1, 1e-5), ("f16", 1, 1e-3),
+                                            ("bf16", 3, 1e-4), ("fp8", 3, 1e-2)])
+def test_fd_reduced_map_forms(fcase, form, split, tol):
+    pm, af = fcase["plan"].search(fcase["echo_dev"], form, split)
+    near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), fcase["P_fd"], tol)
+
+
+def test_fd_fft_form_where_supported(fcase):
+    p = fcase["plan"]
+    if fcase["grid"].M & (fcase["grid"].M - 1):
+        pytest.skip("FFT form needs a power-of-two M")
+    pm, af = p.search(fcase["echo_dev"], "f32fft", 1)
+    near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), fcase["P_fd"], 1e-5)
+
+
+def test_fd_equals_td_on_integer_walks():
+    """R = 2, M = 8: the coarse centre 16 walks exactly m bins at pulse m, so
+    both compensations give the same rows; the other cell walks 18 m / 16
+    bins and they differ."""
+    from paper_2403_06788_amd.plan import Plan
+    r = Radar(2.0e7, 1.0e7, 100.0)
+    dv = make_grid(r, 8, 40, 1, [Axis(0.0, 0.0)]).steps[0]
+    axes = [(15 * dv, 18 * dv)]
+    g = make_grid(r, 8, 40, 1, [Axis(*axes[0])])
+    rng = np.random.default_rng(12)
+    e = (rng.standard_normal((8, 40)) + 1j * rng.standard_normal((8, 40))).astype(np.complex64)
+    ed = torch.from_numpy(e).cuda()
+    ytd = Plan(2.0e7, 1.0e7, 100.0, 8, 40, 1, axes).mgift(ed).cpu().numpy()
+    yfd = Plan(2.0e7, 1.0e7, 100.0, 8, 40, 1, axes, mgift="fd").mgift(ed).cpu().numpy()
+    assert np.abs(yfd[0] - ytd[0]).max() <= 1e-5 * np.abs(ytd).max()
+    assert np.abs(yfd[1] - ytd[1]).max() > 0.1
+    ref = OF.mgift_fd(e, g, 1)
+    assert np.abs(yfd[1] - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_fd_config3_sampled_rows():
+    """M = 1024, N = 4096 (N' = 8192) in the benchmark's batching: f16 x1 on
+    two cells, sampled rows against the frequency-domain oracle."""
+    import synth
+    from paper_2403_06788_amd.plan import Plan
+    case = synth.config_case(3)
+    c = synth.CONFIGS[3]
+    r = c["radar"]
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"], mgift="fd")
+    g = make_grid(Radar(r.fc, r.fs, r.prf), c["M"], c["N"], c["order"],
+                  [Axis(*a) for a in c["axes"]])
+    echo = torch.from_numpy(case["echo"]).cuda()
+    cells = [7, 1800]
+    pm, af = plan.search(echo, "f16", 1, cells=torch.tensor(cells, dtype=torch.int64))
+    pm, af = pm.cpu().numpy(), af.cpu().numpy()
+    Np = OF.pad_length(g)
+    assert Np == 8192
+    S = OF.range_spectrum(case["echo"], Np)
+    F = OT.fine_matrix(g)
+    rows = np.random.default_rng(4).choice(g.rows, 24, replace=False)
+    P = [np.abs(OF.mgift_fd(case["echo"], g, k, Np, S)[:, rows].T @ F) ** 2 for k in cells]
+    scale = max(float(x.max()) for x in P)
+    for i, k in enumerate(cells):
+        err = np.abs(pm[i, rows] - P[i].max(axis=1)).max() / scale
+        assert err <= 1e-3, (k, err)
