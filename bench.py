@@ -103,10 +103,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for rocprofv3 counter passes")
-    ap.add_argument("--workload", type=int, default=3, choices=(3, 4, 5),
+    ap.add_argument("--workload", type=int, default=3, choices=(3, 4, 5, 6),
                     help="3: the M=1024 search (default, headline metric); "
                          "4: adjoint at M=512; 5: third-order search at M=2048 "
-                         "on a 64-coarse-cell subset")
+                         "on a 64-coarse-cell subset; 6: Monte-Carlo detection "
+                         "probability vs SNR (M=256)")
+    ap.add_argument("--trials", type=int, default=100,
+                    help="Monte-Carlo trials per SNR point (workload 6)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -125,6 +128,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == 5:
         return bench_jerk(args)
+    if args.workload == 6:
+        return bench_pd(args)
     case = synth.config_case(3)
     c = synth.CONFIGS[3]
     r = c["radar"]
@@ -452,6 +457,101 @@ def bench_jerk(args):
                               for k, v in res.items() if k != "f32x1"}}
     print(json.dumps(out), flush=True)
 
+
+
+
+PD_PFA = 1e-8          # per-cell false-alarm probability of the LRT threshold
+PD_DETECTORS = ("ds_td", "ds_fd", "grft")
+
+
+def pd_trial(plans, echo, target, gamma2):
+    """Detection statistics of one trial: for each detector, the largest
+    reduced power over the target's coarse cell and its two neighbours along
+    v, in range rows round(r0 / dr) +- 2, and whether it exceeds gamma2.
+    DS-GRFT uses the f16 MFMA form; the single-scale TD-GRFT runs in FP32."""
+    import numpy as np
+    p = plans["ds_td"]
+    ks = []
+    for q, val in enumerate((target.v, target.a)):
+        k = int(np.floor((val / p.step[q] - p.i_lo[q] + 0.5) / p.R))
+        ks.append(min(max(k, 0), p.K[q] - 1))
+    kt = ks[1] * p.K[0] + ks[0]
+    lo, hi = max(0, ks[0] - 1), min(p.K[0] - 1, ks[0] + 1)
+    cells = list(range(ks[1] * p.K[0] + lo, ks[1] * p.K[0] + hi + 1))
+    rb = int(round(target.r0 / p.dr))
+    r0, r1 = max(0, rb - 2), min(p.rows, rb + 3)
+    out = {}
+    for name in PD_DETECTORS:
+        if name == "grft":
+            pm, _ = p.grft(echo, cells[0], len(cells))
+        else:
+            pm, _ = plans[name].search(echo, "f16", 1, cc_begin=cells[0], n=len(cells))
+        stat = float(pm[:, r0:r1].max())
+        out[name] = (stat, stat > gamma2)
+    return out, cells, (r0, r1), kt
+
+
+def bench_pd(args):
+    """Monte-Carlo detection probability vs per-pulse SNR (the shape of the
+    paper's Exp. 2): one random target per trial (uniform r0, v, a), sigma^2 = 1
+    noise, LRT threshold at P_FA = 1e-8 per cell, for DS-GRFT with the
+    time-domain gather, DS-GRFT with the frequency-domain mGIFT and
+    single-scale TD-GRFT; noise-only trials give the false-alarm rate of the
+    neighbourhood test."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_06788_amd.plan import Plan
+    sc = synth.PD_SCENARIO
+    r = sc["radar"]
+    plans = {"ds_td": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"]),
+             "ds_fd": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"],
+                           mgift="fd")}
+    gamma2 = plans["ds_td"].threshold(1.0, PD_PFA)
+    rng = np.random.Generator(np.random.PCG64(2406))
+    snrs = [None] + [float(x) for x in np.arange(-16.0, -3.9, 1.0)]
+    curves = {d: [] for d in PD_DETECTORS}
+    t0 = time.perf_counter()
+    n_trials = 0
+    for snr in snrs:
+        hits = {d: 0 for d in PD_DETECTORS}
+        for _ in range(args.trials):
+            tg = synth.draw_targets(rng, r, sc["M"], sc["N"], 1,
+                                    -200.0 if snr is None else snr, 1.0,
+                                    sc["v"], sc["a"], sc["j"])[0]
+            echo_np = synth.make_echo(r, sc["M"], sc["N"], [] if snr is None else [tg], 1.0, rng)
+            echo = torch.from_numpy(echo_np).cuda()
+            res, _, _, _ = pd_trial(plans, echo, tg, gamma2)
+            for d in PD_DETECTORS:
+                hits[d] += int(res[d][1])
+            n_trials += 1
+        for d in PD_DETECTORS:
+            curves[d].append(hits[d] / args.trials)
+        log(f"snr {snr}: " + ", ".join(f"{d} {hits[d] / args.trials:.2f}" for d in PD_DETECTORS))
+    dt = time.perf_counter() - t0
+
+    def snr_at(pd_curve, level):
+        xs, ys = snrs[1:], pd_curve[1:]
+        for i in range(1, len(xs)):
+            if ys[i - 1] < level <= ys[i]:
+                return xs[i - 1] + (level - ys[i - 1]) / (ys[i] - ys[i - 1]) * (xs[i] - xs[i - 1])
+        return None
+    at = {d: {"pd_0.5": snr_at(curves[d], 0.5), "pd_0.9": snr_at(curves[d], 0.9)}
+          for d in PD_DETECTORS}
+    loss = None
+    if at["ds_td"]["pd_0.9"] is not None and at["ds_fd"]["pd_0.9"] is not None:
+        loss = at["ds_td"]["pd_0.9"] - at["ds_fd"]["pd_0.9"]
+    out = {"metric": "Monte-Carlo trials/s (3 detectors, M=256)", "value": n_trials / dt,
+           "unit": "trials/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "vs_baseline": None,
+           "config": {"workload": "Pd vs per-pulse SNR, M=256 pulses, N=512 bins, P=2, "
+                                  "v +-300 m/s, a +-50 m/s^2, one target per trial, "
+                                  f"{args.trials} trials per point, P_FA {PD_PFA} per cell"},
+           "snr_db": snrs[1:], "false_alarm_rate": {d: curves[d][0] for d in PD_DETECTORS},
+           "pd": {d: curves[d][1:] for d in PD_DETECTORS}, "snr_at": at,
+           "td_minus_fd_db_at_pd_0.9": loss}
+    print(json.dumps(out), flush=True)
 
 if __name__ == "__main__":
     main()

@@ -56,6 +56,12 @@ class Target:
 _R1 = RadarParams(fc=1.0e9, fs=1.0e7, prf=500.0)
 
 # The five workload configurations (radar, sizes, search axes, targets).
+# Detection-probability scenario (Monte-Carlo sweep): one target per trial,
+# range walk up to ~10 bins, noise sigma^2 = 1.
+PD_SCENARIO = dict(radar=_R1, M=256, N=512, order=2,
+                   axes=((-300.0, 300.0), (-50.0, 50.0)),
+                   v=(-300.0, 300.0), a=(-50.0, 50.0), j=(0.0, 0.0))
+
 CONFIGS = {
     1: dict(radar=_R1, M=64, N=256, order=1, axes=((-150.0, 150.0),),
             n_targets=1, snr_db=0.0, r0_bins=(50.0, 200.0),
