@@ -72,19 +72,19 @@ __device__ inline Tap make_tap(const AdjCtx &c, const double *th, const int64_t 
   return T;
 }
 
-// sinc(d) and its derivative for d = x - n with x = xi + xf.
-__device__ inline void sinc_pair(const Tap &T, int n, double &w, double &dw) {
-  const double d = (double)(T.xi - n) + T.xf;
-  const double sg = ((T.xi - n) & 1) ? -1.0 : 1.0;
-  if (fabs(d) < 1e-4) {
-    const double pd = M_PI * d;
-    w = 1.0 - pd * pd / 6.0;
-    dw = -(M_PI * M_PI) * d / 3.0 + (M_PI * M_PI * M_PI * M_PI) * d * d * d / 30.0;
-  } else {
-    const double r = 1.0 / d;
-    w = sg * T.sp * r * (1.0 / M_PI);
-    dw = (sg * T.cp - w) * r;
-  }
+// 1/d in FP64 for 1e-4 <= |d| < 2^24: single-precision seed and two Newton
+// steps (relative error ~2^-92, below FP64 rounding).
+__device__ inline double recip(double d) {
+  double r = (double)__builtin_amdgcn_rcpf((float)d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// sinc(d) and d sinc(d)/dd near d = 0 (|d| < 1e-4), by their series.
+__device__ inline void sinc_series(double d, double &w, double &dw) {
+  const double pd = M_PI * d;
+  w = 1.0 - pd * pd / 6.0;
+  dw = -(M_PI * M_PI) * d / 3.0 + (M_PI * M_PI * M_PI * M_PI) * d * d * d / 30.0;
 }
 
 __device__ inline double block_sum(double v, double *red) {
@@ -97,18 +97,16 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
-// Computes, for candidates th[0..CB), the 8 complex sums (Y, dY/dr0, sum s~ e t,
-// sum s~ e t^2) into out[CB][8] (all threads receive them).
+// Computes, for the candidates s_th[0..nb) (in LDS), the 8 complex sums (Y,
+// dY/dr0, sum s~ e t, sum s~ e t^2) into out[CB][8] (all threads receive
+// them).
 __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
-                           const double (*th)[3], int nb, double (*out)[8],
+                           const double (*s_th)[3], int nb, double (*out)[8],
                            Tap *s_tap, double *red) {
-  int64_t ic[CB][2];
-  for (int b = 0; b < CB; ++b) {
-    if (b < nb) centre_of(c, th[b][1], th[b][2], ic[b]);
-    else ic[b][0] = ic[b][1] = 0;
-  }
   double acc[CB][8];
+#pragma unroll
   for (int b = 0; b < CB; ++b)
+#pragma unroll
     for (int q = 0; q < 8; ++q) acc[b][q] = 0.0;
   const int tid = threadIdx.x;
   for (int m0 = 0; m0 < c.M; m0 += MCH) {
@@ -116,45 +114,75 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
     {
       const int b = tid / MCH, mm = tid % MCH;   // CB * MCH == TPB
       const int m = m0 + mm;
-      if (b < nb && m < c.M) s_tap[tid] = make_tap(c, th[b], ic[b], m);
+      if (b < nb && m < c.M) {
+        const double th[3] = {s_th[b][0], s_th[b][1], s_th[b][2]};
+        int64_t ic[2];
+        centre_of(c, th[1], th[2], ic);
+        s_tap[tid] = make_tap(c, th, ic, m);
+      }
     }
     __syncthreads();
     const int mend = (c.M - m0) < MCH ? (c.M - m0) : MCH;
     for (int mm = 0; mm < mend; ++mm) {
       const float2 *row = echo + (int64_t)(m0 + mm) * c.N;
-      double sr[CB], si[CB], dr_[CB], di[CB];
-      for (int b = 0; b < CB; ++b) sr[b] = si[b] = dr_[b] = di[b] = 0.0;
-      for (int n = tid; n < c.N; n += TPB) {
+      // taps n = tid + TPB j: with TPB even the sign (-1)^(xi - n) of
+      // sin(pi (x - n)) = (-1)^(xi - n) sin(pi xf) is fixed per thread, and
+      // d = x - n steps by exactly -TPB.
+      double sr[CB], si[CB], dr_[CB], di[CB], A[CB], Bc[CB], d0[CB];
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        sr[b] = si[b] = dr_[b] = di[b] = 0.0;
+        const Tap &T = s_tap[b * MCH + mm];
+        const double sg = ((T.xi - tid) & 1) ? -1.0 : 1.0;
+        A[b] = sg * T.sp * (1.0 / M_PI);
+        Bc[b] = sg * T.cp;
+        d0[b] = (double)(T.xi - tid) + T.xf;
+      }
+      int j = 0;
+      for (int n = tid; n < c.N; n += TPB, ++j) {
         const float2 s = row[n];
+        const double sx = (double)s.x, sy = (double)s.y;
+#pragma unroll
         for (int b = 0; b < CB; ++b) {
-          if (b >= nb) break;
-          double w, dw;
-          sinc_pair(s_tap[b * MCH + mm], n, w, dw);
-          sr[b] = fma((double)s.x, w, sr[b]);
-          si[b] = fma((double)s.y, w, si[b]);
-          dr_[b] = fma((double)s.x, dw, dr_[b]);
-          di[b] = fma((double)s.y, dw, di[b]);
+          if (b < nb) {
+            const double d = d0[b] - (double)(TPB * j);
+            double w, dw;
+            if (fabs(d) < 1e-4) {
+              sinc_series(d, w, dw);
+            } else {
+              const double r = recip(d);
+              w = A[b] * r;
+              dw = (Bc[b] - w) * r;
+            }
+            sr[b] = fma(sx, w, sr[b]);
+            si[b] = fma(sy, w, si[b]);
+            dr_[b] = fma(sx, dw, dr_[b]);
+            di[b] = fma(sy, dw, di[b]);
+          }
         }
       }
+#pragma unroll
       for (int b = 0; b < CB; ++b) {
-        if (b >= nb) break;
-        const Tap &T = s_tap[b * MCH + mm];
-        // (sr + j si) * (er + j ei)
-        const double yr = sr[b] * T.er - si[b] * T.ei;
-        const double yi = sr[b] * T.ei + si[b] * T.er;
-        const double gr = dr_[b] * T.er - di[b] * T.ei;
-        const double gi = dr_[b] * T.ei + di[b] * T.er;
-        acc[b][0] += yr;
-        acc[b][1] += yi;
-        acc[b][2] += gr;
-        acc[b][3] += gi;
-        acc[b][4] += yr * T.t;
-        acc[b][5] += yi * T.t;
-        acc[b][6] += yr * T.t * T.t;
-        acc[b][7] += yi * T.t * T.t;
+        if (b < nb) {
+          const Tap &T = s_tap[b * MCH + mm];
+          // (sr + j si) * (er + j ei)
+          const double yr = sr[b] * T.er - si[b] * T.ei;
+          const double yi = sr[b] * T.ei + si[b] * T.er;
+          const double gr = dr_[b] * T.er - di[b] * T.ei;
+          const double gi = dr_[b] * T.ei + di[b] * T.er;
+          acc[b][0] += yr;
+          acc[b][1] += yi;
+          acc[b][2] += gr;
+          acc[b][3] += gi;
+          acc[b][4] += yr * T.t;
+          acc[b][5] += yi * T.t;
+          acc[b][6] += yr * T.t * T.t;
+          acc[b][7] += yi * T.t * T.t;
+        }
       }
     }
   }
+#pragma unroll
   for (int b = 0; b < CB; ++b)
     for (int q = 0; q < 8; ++q) out[b][q] = block_sum(acc[b][q], red);
 }
@@ -179,20 +207,26 @@ __global__ __launch_bounds__(TPB) void k_adj_fwd(AdjCtx c, const float2 *__restr
                                                  double *__restrict__ saved) {
   __shared__ Tap s_tap[TPB];
   __shared__ double red[TPB / 64];
+  __shared__ double s_th[CB][3];
   const int b0 = blockIdx.x * CB;
   const int nb = (B - b0) < CB ? (B - b0) : CB;
-  double th[CB][3];
-  for (int b = 0; b < CB; ++b)
-    for (int q = 0; q < 3; ++q) th[b][q] = (b < nb) ? theta[(b0 + b) * 3 + q] : 0.0;
+  if (threadIdx.x < CB * 3) {
+    const int b = threadIdx.x / 3, q = threadIdx.x % 3;
+    s_th[b][q] = (b < nb) ? theta[(b0 + b) * 3 + q] : 0.0;
+  }
   double out[CB][8];
-  eval_block(c, echo, th, nb, out, s_tap, red);
+  eval_block(c, echo, s_th, nb, out, s_tap, red);
   if (threadIdx.x == 0) {
-    for (int b = 0; b < nb; ++b) {
-      double sv[8];
-      finish(c, out[b], sv);
-      J[b0 + b] = sv[0] * sv[0] + sv[1] * sv[1];
-      if (saved)
-        for (int q = 0; q < 8; ++q) saved[(int64_t)(b0 + b) * 8 + q] = sv[q];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      if (b < nb) {
+        double sv[8];
+        finish(c, out[b], sv);
+        J[b0 + b] = sv[0] * sv[0] + sv[1] * sv[1];
+        if (saved)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) saved[(int64_t)(b0 + b) * 8 + q] = sv[q];
+      }
     }
   }
 }
@@ -253,22 +287,16 @@ __global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__rest
     const int bend = (B - bb) < TPB ? (B - bb) : TPB;
     for (int k = 0; k < bend; ++k) {
       const BTap q = s_b[k];
-      Tap T;
-      T.xf = q.xf;
-      T.sp = q.sp;
-      T.cp = 0.0;
-      T.xi = q.xi;
+      // n = n0 + tid + TPB e with n0 and TPB even: fixed sign per thread
+      const double sg = ((q.xi - tid) & 1) ? -1.0 : 1.0;
+      const double A = sg * q.sp * (1.0 / M_PI);
+      const double d0 = (double)(q.xi - n0 - tid) + q.xf;
+#pragma unroll
       for (int e = 0; e < PER; ++e) {
-        const int n = n0 + tid + TPB * e;
-        const double d = (double)(q.xi - n) + q.xf;
-        double w;
-        if (fabs(d) < 1e-4) {
-          const double pd = M_PI * d;
-          w = 1.0 - pd * pd / 6.0;
-        } else {
-          const double sg = ((q.xi - n) & 1) ? -1.0 : 1.0;
-          w = sg * q.sp / (M_PI * d);
-        }
+        const double d = d0 - (double)(TPB * e);
+        double w, dw;
+        if (fabs(d) < 1e-4) sinc_series(d, w, dw);
+        else w = A * recip(d);
         ar[e] = fma(w, q.cr, ar[e]);
         ai[e] = fma(w, q.ci, ai[e]);
       }
@@ -290,16 +318,22 @@ __global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restri
                                                 double *__restrict__ Jout) {
   __shared__ Tap s_tap[TPB];
   __shared__ double red[TPB / 64];
+  __shared__ double s_th[CB][3];
   const int b0 = blockIdx.x * CB;
   const int nb = (B - b0) < CB ? (B - b0) : CB;
+  // every thread keeps the same per-candidate state; thread 0 publishes the
+  // point to evaluate through s_th
   double th[CB][3], lo[CB][3], hi[CB][3], rho[CB], J[CB];
   const double sc[3] = {c.dr, c.st0, c.st1};
+#pragma unroll
   for (int b = 0; b < CB; ++b) {
+#pragma unroll
     for (int q = 0; q < 3; ++q) th[b][q] = (b < nb) ? theta[(b0 + b) * 3 + q] : 0.0;
     int64_t ic[2];
     centre_of(c, th[b][1], th[b][2], ic);
     lo[b][0] = 0.0;
     hi[b][0] = (double)(c.N - 1) * c.dr;
+#pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (p < c.P) {
         // continuous fine index range of the coarse cell, kept 1e-6 inside
@@ -311,38 +345,57 @@ __global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restri
         lo[b][1 + p] = hi[b][1 + p] = 0.0;
       }
     }
+#pragma unroll
     for (int q = 0; q < 3; ++q) th[b][q] = fmin(fmax(th[b][q], lo[b][q]), hi[b][q]);
     rho[b] = 0.5;
   }
+  auto publish = [&](const double (&pt)[CB][3]) {
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s_th[b][q] = pt[b][q];
+    __syncthreads();
+  };
   double out[CB][8], sv[CB][8];
-  eval_block(c, echo, th, nb, out, s_tap, red);
-  for (int b = 0; b < nb; ++b) {
+  publish(th);
+  eval_block(c, echo, s_th, nb, out, s_tap, red);
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
     finish(c, out[b], sv[b]);
     J[b] = sv[b][0] * sv[b][0] + sv[b][1] * sv[b][1];
   }
   for (int it = 0; it < iters; ++it) {
     double prop[CB][3];
+#pragma unroll
     for (int b = 0; b < CB; ++b) {
       double g[3], gn = 0.0;
+#pragma unroll
       for (int p = 0; p < 3; ++p) {
         g[p] = (b < nb) ? 2.0 * (sv[b][0] * sv[b][2 + 2 * p] + sv[b][1] * sv[b][3 + 2 * p]) * sc[p]
                         : 0.0;
         gn += g[p] * g[p];
       }
       gn = sqrt(gn);
+#pragma unroll
       for (int p = 0; p < 3; ++p) {
         const double z = (gn > 0.0) ? th[b][p] + rho[b] * g[p] / gn * sc[p] : th[b][p];
         prop[b][p] = fmin(fmax(z, lo[b][p]), hi[b][p]);
       }
     }
     double po[CB][8];
-    eval_block(c, echo, prop, nb, po, s_tap, red);
-    for (int b = 0; b < nb; ++b) {
+    publish(prop);
+    eval_block(c, echo, s_th, nb, po, s_tap, red);
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
       double ps[8];
       finish(c, po[b], ps);
       const double Jp = ps[0] * ps[0] + ps[1] * ps[1];
-      if (Jp >= J[b]) {
+      if (b < nb && Jp >= J[b]) {
+#pragma unroll
         for (int p = 0; p < 3; ++p) th[b][p] = prop[b][p];
+#pragma unroll
         for (int q = 0; q < 8; ++q) sv[b][q] = ps[q];
         J[b] = Jp;
         rho[b] = fmin(2.0 * rho[b], 2.0);
@@ -352,9 +405,13 @@ __global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restri
     }
   }
   if (threadIdx.x == 0) {
-    for (int b = 0; b < nb; ++b) {
-      for (int q = 0; q < 3; ++q) theta[(b0 + b) * 3 + q] = th[b][q];
-      if (Jout) Jout[b0 + b] = J[b];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      if (b < nb) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) theta[(b0 + b) * 3 + q] = th[b][q];
+        if (Jout) Jout[b0 + b] = J[b];
+      }
     }
   }
 }
