@@ -8,10 +8,11 @@
  * (M pulses x N range bins), radar parameters (f_c, f_s, PRF) and motion
  * parameter extents go in; a detection map and peak parameters come out.
  * The search evaluates, for every coarse cell c_c of the dual-scale lattice
- * (Sec. IV-B, eqs. (48)-(52)), the time-domain mGIFT (gather of each pulse's
- * range bin along the coarse walk and the pre-DFM de-ramp, eqs. (46)-(47),
- * Alg. 1) followed by the GFT over the cell's fine space (eq. (44), Alg. 2),
- * and reduces |.|^2 over the fine space (eq. (72)).
+ * (Sec. IV-B, eqs. (48)-(52)), the mGIFT (eqs. (46)-(47), Alg. 1: by default
+ * in the time domain, a gather of each pulse's range bin along the coarse
+ * walk and the pre-DFM de-ramp; optionally in the frequency domain) followed
+ * by the GFT over the cell's fine space (eq. (44), Alg. 2, as a GEMM or as a
+ * slow-time FFT), and reduces |.|^2 over the fine space (eq. (72)).
  *
  * Conventions shared by every entry point
  *  - Complex data are interleaved (re, im) pairs: complex64 = 2 x float,
@@ -172,7 +173,9 @@ dsgrft_status dsgrft_mgift(dsgrft_plan plan, const void *d_echo,
 /* DS-GRFT search (stages a1..a4, Alg. 3): for each listed coarse cell and
  * range row, the largest |Y|^2 over the cell's fine space and the smallest
  * fine index attaining it (ties to the smaller index).  Cells are
- * d_cells[0..n) (device int64 list) or, when d_cells is NULL,
+ * d_cells[0..n) (device int64 list, each in [0, n_coarse): other values
+ * give unspecified results but no access outside the plan's and the
+ * caller's buffers) or, when d_cells is NULL,
  * cc_begin..cc_begin+n-1.  Outputs d_pmax, d_argf: [n][rows] (float, int32).
  * `form`/`split`: see dsgrft_form; FP32 requires split = 1.  The echo must
  * stay unchanged until the stream reaches the end of this call. */
