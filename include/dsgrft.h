@@ -116,6 +116,8 @@ typedef struct {
   double lambda, dr, T;  /* wavelength, range bin, integration time       */
   double step[3];        /* fine steps dv, da, dj                         */
   size_t workspace_bytes;/* device memory held by the plan                */
+  int32_t fd_pad;        /* N' of the frequency-domain mGIFT (0 if the    */
+                         /*   plan uses the time-domain gather)           */
 } dsgrft_plan_info;
 
 typedef struct {

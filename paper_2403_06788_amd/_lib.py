@@ -47,7 +47,8 @@ class PlanInfo(C.Structure):
                 ("rows", C.c_int32), ("n_coarse", C.c_int64),
                 ("n_fine", C.c_int64), ("lambda_", C.c_double),
                 ("dr", C.c_double), ("T", C.c_double),
-                ("step", C.c_double * 3), ("workspace_bytes", C.c_size_t)]
+                ("step", C.c_double * 3), ("workspace_bytes", C.c_size_t),
+                ("fd_pad", C.c_int32)]
 
 
 class Profile(C.Structure):

@@ -363,6 +363,7 @@ dsgrft_status dsgrft_plan_get_info(dsgrft_plan p, dsgrft_plan_info *o) {
   o->dr = p->dr;
   o->T = p->T;
   o->workspace_bytes = p->ws_bytes;
+  o->fd_pad = p->fd ? p->fd_np : 0;
   return DSGRFT_OK;
 }
 

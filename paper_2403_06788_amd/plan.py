@@ -71,6 +71,7 @@ class Plan:
         self.lam, self.dr, self.T = info.lambda_, info.dr, info.T
         self.step = tuple(info.step)
         self.workspace_bytes = info.workspace_bytes
+        self.fd_pad = info.fd_pad
         self.prf = prf
         self.mgift_mode = mgift
 

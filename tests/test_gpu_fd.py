@@ -23,6 +23,11 @@ def fcase(request):
     return c
 
 
+def test_fd_pad_length_matches_oracle(fcase):
+    assert fcase["plan"].fd_pad == OF.pad_length(fcase["grid"])
+    assert plan_for(fcase).fd_pad == 0
+
+
 def test_fd_mgift_rows_match_oracle(fcase):
     g = fcase["grid"]
     y = fcase["plan"].mgift(fcase["echo_dev"]).cpu().numpy()
@@ -89,7 +94,7 @@ def test_fd_config3_sampled_rows():
     pm, af = plan.search(echo, "f16", 1, cells=torch.tensor(cells, dtype=torch.int64))
     pm, af = pm.cpu().numpy(), af.cpu().numpy()
     Np = OF.pad_length(g)
-    assert Np == 8192
+    assert Np == plan.fd_pad == 8192
     S = OF.range_spectrum(case["echo"], Np)
     F = OT.fine_matrix(g)
     rows = np.random.default_rng(4).choice(g.rows, 24, replace=False)
