@@ -12,9 +12,9 @@
 // sinpi(frac(x)) / (pi (x - n)), with a series near zero.
 //
 // Forward: a workgroup of 256 threads takes CB candidates; per chunk of 64
-// pulses the per-(candidate, pulse) quantities are formed once into LDS, and
-// each thread then sweeps its share of range taps for all CB candidates,
-// reusing every echo load CB times.  Accumulated per thread: Y, dY/dr0 (with
+// pulses the per-(candidate, pulse) quantities are formed once into LDS; each
+// group of 64 threads then takes every fourth pulse and sweeps its range taps
+// for all CB candidates, reusing every echo load CB times.  Accumulated per thread: Y, dY/dr0 (with
 // sinc'), sum s~ e t and sum s~ e t^2 (for dY/dv, dY/da), reduced at the end.
 #include "internal.h"
 
@@ -123,29 +123,34 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
     }
     __syncthreads();
     const int mend = (c.M - m0) < MCH ? (c.M - m0) : MCH;
-    for (int mm = 0; mm < mend; ++mm) {
+    // pulse group pg = tid / 64 takes every fourth pulse of the chunk; its 64
+    // lanes sweep the range taps n = lane + 64 j of that pulse.  The partial
+    // sums are linear in the taps, so each thread multiplies its own share by
+    // the pulse phasor and the block reduction at the end completes them.
+    const int pg = tid >> 6, lane = tid & 63;
+    for (int mm = pg; mm < mend; mm += TPB / 64) {
       const float2 *row = echo + (int64_t)(m0 + mm) * c.N;
-      // taps n = tid + TPB j: with TPB even the sign (-1)^(xi - n) of
+      // with the tap stride 64 even, the sign (-1)^(xi - n) of
       // sin(pi (x - n)) = (-1)^(xi - n) sin(pi xf) is fixed per thread, and
-      // d = x - n steps by exactly -TPB.
+      // d = x - n steps by exactly -64.
       double sr[CB], si[CB], dr_[CB], di[CB], A[CB], Bc[CB], d0[CB];
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         sr[b] = si[b] = dr_[b] = di[b] = 0.0;
         const Tap &T = s_tap[b * MCH + mm];
-        const double sg = ((T.xi - tid) & 1) ? -1.0 : 1.0;
+        const double sg = ((T.xi - lane) & 1) ? -1.0 : 1.0;
         A[b] = sg * T.sp * (1.0 / M_PI);
         Bc[b] = sg * T.cp;
-        d0[b] = (double)(T.xi - tid) + T.xf;
+        d0[b] = (double)(T.xi - lane) + T.xf;
       }
       int j = 0;
-      for (int n = tid; n < c.N; n += TPB, ++j) {
+      for (int n = lane; n < c.N; n += 64, ++j) {
         const float2 s = row[n];
         const double sx = (double)s.x, sy = (double)s.y;
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
           if (b < nb) {
-            const double d = d0[b] - (double)(TPB * j);
+            const double d = d0[b] - (double)(64 * j);
             double w, dw;
             if (fabs(d) < 1e-4) {
               sinc_series(d, w, dw);

@@ -11,8 +11,8 @@
 //  * MFMA forms: B-operand fragments of v_mfma_f32_32x32x16_{f16,bf16}:
 //    planes (re_hi, im_hi[, re_lo, im_lo]) x (rows_p/32) row blocks x
 //    (Mp/16) pulse blocks x 64 lanes x 8 elements; lane l holds row
-//    32 nb + l % 32 and pulses 16 kb + 8 (l / 32) + e.  One wave writes one
-//    1 KiB fragment per plane, contiguously.
+//    32 nb + l % 32 and pulses 16 kb + 8 (l / 32) + e.  A wave writes whole
+//    1 KiB fragments per plane, contiguously.
 //  * 8-bit form: B-operand fragments of v_mfma_scale_f32_32x32x64_f8f6f4
 //    (OCP e4m3), K blocks of 64 pulses, 2 KiB each as two halves
 //    [e / 16][lane][e % 16], lane l holding row 32 nb + l % 32 and pulses
@@ -75,48 +75,67 @@ __device__ inline uint16_t b16(T x) {
   return __builtin_bit_cast(uint16_t, x);
 }
 
+// One workgroup per (unit, row block of 32 rows, 4 KPW pulse blocks): the
+// offsets and de-ramp phasors of its 64 KPW pulses are staged in LDS, then
+// wave w writes the fragments of pulse blocks kb0 + w KPW .. + KPW - 1, so
+// each lane has 8 KPW independent echo loads in flight.
+constexpr int KPW = 4;
+
 template <typename T, int NP>
 __global__ __launch_bounds__(256) void k_gather_lp(
     const float2 *__restrict__ echo, const int32_t *__restrict__ off,
     const float2 *__restrict__ psi, int M, int N, int Mp, int rows, int n_begin,
     int64_t estride, int NB, int KB, int64_t nunits, uint4 *__restrict__ G) {
-  const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (w >= nunits * NB * KB) return;
-  const int kb = (int)(w % KB);
-  const int nb = (int)((w / KB) % NB);
-  const int64_t u = w / ((int64_t)KB * NB);
-  const int r = nb * 32 + (lane & 31);
-  const int m0 = kb * 16 + 8 * (lane >> 5);
-  echo += u * estride;
-  uint16_t re_h[8], im_h[8], re_l[8], im_l[8];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    int m = m0 + e;
-    float2 v = make_float2(0.f, 0.f);
-    if (m < M && r < rows) {
-      int64_t um = u * Mp + m;
-      v = cmul(sample(echo, N, m, n_begin + r + off[um]), psi[um]);
-    }
-    T hr = (T)v.x, hi = (T)v.y;
-    re_h[e] = b16(hr);
-    im_h[e] = b16(hi);
-    if (NP == 4) {
-      re_l[e] = b16((T)(v.x - (float)hr));
-      im_l[e] = b16((T)(v.y - (float)hi));
-    }
+  constexpr int PW = 4 * KPW * 16;  // pulses per workgroup
+  __shared__ int32_t s_off[PW];
+  __shared__ float2 s_psi[PW];
+  const int KG = (KB + 4 * KPW - 1) / (4 * KPW);
+  const int kg = (int)(blockIdx.x % KG);
+  const int nb = (int)((blockIdx.x / KG) % NB);
+  const int64_t u = blockIdx.x / ((int64_t)KG * NB);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mw0 = kg * PW;
+  {
+    const int m = mw0 + tid;
+    s_off[tid] = (m < Mp) ? off[u * Mp + m] : 0;
+    s_psi[tid] = (m < Mp) ? psi[u * Mp + m] : make_float2(0.f, 0.f);
   }
+  __syncthreads();
+  echo += u * estride;
+  const int r = nb * 32 + (lane & 31);
+  const int64_t plane = (int64_t)NB * KB * 64;
   auto pack = [](const uint16_t *h) {
     return make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
                       h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
   };
-  const int64_t plane = (int64_t)NB * KB * 64;
-  const int64_t o = ((u * NP) * NB + nb) * (int64_t)KB * 64 + (int64_t)kb * 64 + lane;
-  G[o] = pack(re_h);
-  G[o + plane] = pack(im_h);
-  if (NP == 4) {
-    G[o + 2 * plane] = pack(re_l);
-    G[o + 3 * plane] = pack(im_l);
+#pragma unroll
+  for (int i = 0; i < KPW; ++i) {
+    const int kb = kg * 4 * KPW + wave * KPW + i;
+    const int ml0 = (wave * KPW + i) * 16 + 8 * (lane >> 5);  // local pulse
+    uint16_t re_h[8], im_h[8], re_l[8], im_l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ml = ml0 + e, m = mw0 + ml;
+      float2 v = make_float2(0.f, 0.f);
+      if (kb < KB && m < M && r < rows)
+        v = cmul(sample(echo, N, m, n_begin + r + s_off[ml]), s_psi[ml]);
+      T hr = (T)v.x, hi = (T)v.y;
+      re_h[e] = b16(hr);
+      im_h[e] = b16(hi);
+      if (NP == 4) {
+        re_l[e] = b16((T)(v.x - (float)hr));
+        im_l[e] = b16((T)(v.y - (float)hi));
+      }
+    }
+    if (kb < KB) {
+      const int64_t o = ((u * NP) * NB + nb) * (int64_t)KB * 64 + (int64_t)kb * 64 + lane;
+      G[o] = pack(re_h);
+      G[o + plane] = pack(im_h);
+      if (NP == 4) {
+        G[o + 2 * plane] = pack(re_l);
+        G[o + 3 * plane] = pack(im_l);
+      }
+    }
   }
 }
 
@@ -290,8 +309,8 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
 #undef DS_GATHER_F8
     return hipGetLastError();
   }
-  int64_t waves = nunits * p->NB * p->KB;
-  dim3 grid((unsigned)((waves + 3) / 4));
+  const int64_t kg = (p->KB + 4 * KPW - 1) / (4 * KPW);
+  dim3 grid((unsigned)(nunits * p->NB * kg));
 #define DS_GATHER_LP(T, NP)                                                           \
   hipLaunchKernelGGL((k_gather_lp<T, NP>), grid, dim3(256), 0, s, src.echo, p->u_off,   \
                      p->u_psi, p->M, src.N, p->Mp, p->rows, src.n_begin,                \
