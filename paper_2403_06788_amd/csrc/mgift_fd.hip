@@ -13,7 +13,8 @@
 //    x(m) = Num_c(m) / (R M^3) the coarse walk of the unit's cell in bins.
 //    The phase k_s x / NP is formed as ((k_s xi) mod NP) / NP + k_s xf / NP
 //    with xi = floor(x) exact and xf in [0, 1) in FP64; the second factor is
-//    a product of two small FP64-built tables (k_s = 64 a + c).
+//    a product of two small tables (k_s = 64 a + c) whose phases are reduced
+//    in FP64.
 // The rows E[u] then go through the ordinary gathers with zero offsets, which
 // apply the pre-DFM phase (eq. (47)) and write the fine search's layout.
 //
@@ -155,15 +156,15 @@ __global__ __launch_bounds__(256) void k_fd_shift(
   const int64_t num = lat_num(L, m, ic[0], ic[1], ic[2]);
   const int64_t xi = floor_div(num, L.RM3);
   const double xf = (double)(num - xi * L.RM3) / (double)L.RM3;
+  // sub-ramp factors: the turn fractions (|.| <= 1/2) are formed in FP64 and
+  // their sine and cosine taken in FP32 (error ~ FP32 rounding of the result)
   for (int i = tid; i < NA + 64; i += 256) {
-    double s, c;
-    if (i < NA) {
-      sincospi(2.0 * 64.0 * (double)(i - A0) * xf / NP, &s, &c);
-      TA[i] = make_float2((float)c, (float)s);
-    } else {
-      sincospi(2.0 * (double)(i - NA) * xf / NP, &s, &c);
-      TC[i - NA] = make_float2((float)c, (float)s);
-    }
+    const double turns = (i < NA) ? 64.0 * (double)(i - A0) * xf / NP
+                                  : (double)(i - NA) * xf / NP;
+    float s, c;
+    sincospif(2.0f * (float)turns, &s, &c);
+    if (i < NA) TA[i] = make_float2(c, s);
+    else TC[i - NA] = make_float2(c, s);
   }
   __syncthreads();
   const float2 *sp = spec + (int64_t)m * NP;
