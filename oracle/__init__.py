@@ -26,6 +26,9 @@ Modules
             search: operand rounding, power-of-two scales, split products.
   fd        frequency-domain mGIFT (Alg. 1): range spectrum, coarse RM phase
             ramp, IFFT, pre-DFM phase; DS-GRFT on top of it.
+  ktmfp     dual-scale KT-MFP (Alg. 4, P = 2): keystone transform by sinc
+            interpolation over slow time, folding-factor coarse cells, GFT
+            over the baseband velocities and fine accelerations.
 
 Parity status: every function here is pinned by a CPU test (brute force,
 closed forms, invariants, or a library routine); see tests/test_oracle_*.py.
