@@ -75,7 +75,7 @@ typedef enum {
   DSGRFT_FORM_F32_FFT = 4 /* FP32, fine velocities by a slow-time FFT as in
                              Alg. 2 (one per fine acceleration); split 1;
                              M a power of two in [64, 2048], else
-                             E_UNSUPPORTED */
+                             E_UNSUPPORTED; the only form of DS-KT-MFP */
 } dsgrft_form;
 
 typedef struct {
@@ -104,20 +104,47 @@ typedef struct {
                       /*      the range spectrum zero-padded to N' (the   */
                       /*      smallest power of two >= N + walk bound),   */
                       /*      then IFFT; N' <= 16384 else E_UNSUPPORTED   */
+                      /*   2: DS-KT-MFP (Alg. 4, Prop. 3): keystone       */
+                      /*      transform of the same spectrum, then per    */
+                      /*      coarse cell the folding-factor and coarse   */
+                      /*      acceleration compensation of eq. (26) and   */
+                      /*      IFFT; see "DS-KT-MFP plans" below           */
 } dsgrft_config;
+
+/* DS-KT-MFP plans (mgift = 2) need order 2 and M a power of two in
+ * [64, 2048] (else E_UNSUPPORTED).  Their lattice folds the velocity axis
+ * (eq. (23)): a fine velocity index is i1 = q M + i1', i1' in [-M/2, M/2),
+ * with folding factors q = q_lo .. q_lo + n_fold - 1 covering the DS-GRFT
+ * axis indices [i_lo,1, i_lo,1 + K1 R); the acceleration axis keeps the
+ * DS-GRFT coarse cells.  Coarse cell k = k2 n_fold + (q - q_lo) (k2 < K2,
+ * centre i2c = i_lo,2 + k2 R + R/2); fine index f = u2 M + u1, i1' = u1 -
+ * M/2, acceleration index i2c + u2 - R/2, so n_fine = M R.  With the range
+ * spectrum S[m][k] (length N' as in mode 1, signed index k_s) and
+ * eps_k = k_s / (R N' + k_s):
+ *   S_KT[m][k] = sum_{m'<M} S[m'][k] sinc(m - m' - m eps_k),
+ *   y[m][r] = psi(m) (1/N') sum_k S_KT[m][k]
+ *             exp(+j 2 pi (q m eps_k - k_s x2(m)/N' + k (n_begin + r)/N')),
+ *   x2(m) = i2c m^2 / (R M^2), psi(m) = exp(+j 2 pi i2c m^2 M / M^3),
+ *   Y[f][r] = sum_m y[m][r] exp(+j 2 pi (i1' m M^2 + (u2 - R/2) m^2 M) / M^3).
+ * They support dsgrft_mgift (y), dsgrft_search / dsgrft_search_full with
+ * DSGRFT_FORM_F32_FFT, dsgrft_detect and dsgrft_noise_power; the other forms
+ * and entry points return E_UNSUPPORTED. */
 
 typedef struct {
   int32_t R;             /* fine cells per coarse step and order          */
-  int32_t K[3];          /* coarse cells per order (1 above P)            */
+  int32_t K[3];          /* DS-GRFT coarse cells per order (1 above P)    */
   int32_t i_lo[3];       /* first fine lattice index per order            */
   int32_t rows;          /* n_end - n_begin                               */
-  int64_t n_coarse;      /* K1 K2 K3                                      */
-  int64_t n_fine;        /* R^P                                           */
+  int64_t n_coarse;      /* K1 K2 K3 (DS-KT-MFP: n_fold K2)               */
+  int64_t n_fine;        /* R^P (DS-KT-MFP: M R)                          */
   double lambda, dr, T;  /* wavelength, range bin, integration time       */
   double step[3];        /* fine steps dv, da, dj                         */
   size_t workspace_bytes;/* device memory held by the plan                */
   int32_t fd_pad;        /* N' of the frequency-domain mGIFT (0 if the    */
                          /*   plan uses the time-domain gather)           */
+  int32_t kt_q_lo;       /* DS-KT-MFP: first folding factor (else 0)      */
+  int32_t kt_folds;      /* DS-KT-MFP: folding factors n_fold (else 0);   */
+                         /*   n_coarse = n_fold K2                         */
 } dsgrft_plan_info;
 
 typedef struct {
@@ -156,7 +183,8 @@ const char *dsgrft_status_string(dsgrft_status s);
  * cell centre (mGIFT envelope correction, eq. (46)), d_psi[i][m] =
  * exp(+j 2 pi Num/M^3), the pre-DFM phase H_pre-DFM of eq. (47), complex64.
  * Layout [n][M].  The offsets are the nearest-bin walk whatever the plan's
- * mgift mode.  E_INVALID if the range leaves [0, n_coarse). */
+ * mgift mode.  E_INVALID if the range leaves [0, n_coarse); E_UNSUPPORTED
+ * for DS-KT-MFP plans. */
 dsgrft_status dsgrft_coarse_tables(dsgrft_plan plan, int64_t cc_begin,
                                    int64_t n, int32_t *d_off, void *d_psi,
                                    void *stream);
@@ -167,7 +195,8 @@ dsgrft_status dsgrft_coarse_tables(dsgrft_plan plan, int64_t cc_begin,
  * Frequency-domain plans (mgift = 1): y = psi * (1/N') sum_k S'[m][k]
  * exp(+j 2 pi k_s x(m) / N') exp(+j 2 pi k (n_begin + r) / N'), with S' the
  * range DFT of row m zero-padded to N', k_s the signed frequency index and
- * x(m) = Num(m) / (R M^3) the cell's walk in bins (H_RM of eq. (10)). */
+ * x(m) = Num(m) / (R M^3) the cell's walk in bins (H_RM of eq. (10)).
+ * DS-KT-MFP plans (mgift = 2): the y of "DS-KT-MFP plans" above. */
 dsgrft_status dsgrft_mgift(dsgrft_plan plan, const void *d_echo,
                            int64_t cc_begin, int64_t n, void *d_out,
                            void *stream);

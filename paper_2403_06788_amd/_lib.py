@@ -48,7 +48,7 @@ class PlanInfo(C.Structure):
                 ("n_fine", C.c_int64), ("lambda_", C.c_double),
                 ("dr", C.c_double), ("T", C.c_double),
                 ("step", C.c_double * 3), ("workspace_bytes", C.c_size_t),
-                ("fd_pad", C.c_int32)]
+                ("fd_pad", C.c_int32), ("kt_q_lo", C.c_int32), ("kt_folds", C.c_int32)]
 
 
 class Profile(C.Structure):

@@ -45,7 +45,7 @@ void release(dsgrft_plan p) {
   if (!p) return;
   void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->u_off, p->u_psi,
                   p->G, p->g_scale, p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
-                  p->packed, p->det_ws, p->adj_ws};
+                  p->kt_spec, p->kt_invd, p->packed, p->det_ws, p->adj_ws};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -57,6 +57,9 @@ bool on_plan_device(dsgrft_plan p) {
 }
 
 dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
+  if (p->kt && form != DSGRFT_FORM_F32_FFT)
+    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_F32_FFT) ? DSGRFT_E_UNSUPPORTED
+                                                                   : DSGRFT_E_INVALID;
   switch (form) {
     case DSGRFT_FORM_F32:
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
@@ -88,6 +91,7 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
                          float *full, hipStream_t s) {
   const int64_t Bc = p->batch_cells, Bu = p->batch_units;
   if (p->fd) DS_TRY(launch_range_fft(p, echo, s));
+  if (p->kt) DS_TRY(launch_keystone(p, s));
   const GatherSrc src = gather_src(p, echo);
   for (int64_t c0 = 0; c0 < n; c0 += Bc) {
     const int64_t nc = (n - c0) < Bc ? (n - c0) : Bc;
@@ -98,7 +102,10 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
     for (int64_t u0 = 0; u0 < nut; u0 += Bu) {
       const int64_t nu = (nut - u0) < Bu ? (nut - u0) : Bu;
       DS_TRY(launch_unit_tables(p, cl, cc_begin + c0, u0, nu, s));
-      if (p->fd) DS_TRY(launch_fd_shift(p, cl, cc_begin + c0, u0, nu, p->R3, s));
+      if (p->kt)
+        DS_TRY(launch_kt_shift(p, cl, cc_begin + c0, u0, nu, s));
+      else if (p->fd)
+        DS_TRY(launch_fd_shift(p, cl, cc_begin + c0, u0, nu, p->R3, s));
       auto &pr = p->prof;
       const bool tg = pr.ng < pr.cap, tf = pr.nf < pr.cap;
       const double samples = (double)nu * p->rows * p->M;
@@ -183,7 +190,7 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   if (radar->kappa != 1.0) return DSGRFT_E_UNSUPPORTED;
   const int M = cfg->M, N = cfg->N, P = cfg->order;
   if (M < 1 || N < 1 || P < 1 || P > 3 || cfg->batch < 0) return DSGRFT_E_INVALID;
-  if (cfg->mgift != 0 && cfg->mgift != 1) return DSGRFT_E_INVALID;
+  if (cfg->mgift < 0 || cfg->mgift > 2) return DSGRFT_E_INVALID;
   if (M > (1 << 20) || N > (1 << 28)) return DSGRFT_E_INVALID;
   int nb = cfg->n_begin, ne = cfg->n_end;
   if (nb == 0 && ne == 0) ne = N;
@@ -252,10 +259,53 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   p->lat.M = M;
   p->lat.M3 = (int64_t)M3;
   p->lat.RM3 = (int64_t)(R * M3);
-  p->n_coarse = (int64_t)p->K[0] * p->K[1] * p->K[2];
+  p->S0 = (int)R;
+  p->gK0 = p->K[0];
+  p->gilo0 = p->ilo[0];
+  p->fd = cfg->mgift != 0;
+  p->kt = cfg->mgift == 2;
+  if (p->fd) {
+    p->fd_np = fd_pad_length(p);  // from the DS-GRFT lattice in both modes
+    if (p->fd_np > 16384) {
+      delete p;
+      return DSGRFT_E_UNSUPPORTED;
+    }
+  }
   long long nf = 1, C = 1;
   for (int q = 0; q < P; ++q) nf *= R;
   for (int q = 0; q < (P < 2 ? P : 2); ++q) C *= R;
+  if (p->kt) {
+    // DS-KT-MFP lattice (velocity folding, eq. (23)): fine velocity index
+    // i1 = q M + i1', i1' in [-M/2, M/2); the folding factors cover the
+    // axis's indices [i_lo, i_lo + K1 R), the acceleration axis keeps the
+    // DS-GRFT coarse cells, and the fine space is M x R.
+    if (P != 2 || !fft_form_supported(M)) {
+      delete p;
+      return DSGRFT_E_UNSUPPORTED;
+    }
+    const long long i_lo = p->ilo[0], i_hi = i_lo + (long long)p->K[0] * R - 1;
+    const long long q_lo = (long long)floor_div(i_lo + M / 2, M);
+    const long long q_hi = (long long)floor_div(i_hi + M / 2, M);
+    const long long lo0 = q_lo * M - M / 2, top0 = (q_hi + 1) * M - M / 2;
+    const long long mag0 = (lo0 < 0 ? -lo0 : lo0) > (top0 < 0 ? -top0 : top0)
+                               ? (lo0 < 0 ? -lo0 : lo0) : (top0 < 0 ? -top0 : top0);
+    const long long il1 = p->ilo[1], top1 = il1 + (long long)p->K[1] * R;
+    const long long mag1 = (il1 < 0 ? -il1 : il1) > (top1 < 0 ? -top1 : top1)
+                               ? (il1 < 0 ? -il1 : il1) : (top1 < 0 ? -top1 : top1);
+    if (lo0 < -(1LL << 30) || top0 > (1LL << 30) ||
+        2 * ((__int128)mag0 + mag1) * M3 + (__int128)R * M3 >= ((__int128)1 << 62)) {
+      delete p;
+      return DSGRFT_E_INVALID;
+    }
+    p->kt_q_lo = (int)q_lo;
+    p->kt_na = (int)(q_hi - q_lo + 1);
+    p->K[0] = p->kt_na;
+    p->ilo[0] = (int)lo0;
+    p->S0 = M;
+    nf = (long long)M * R;
+    C = nf;
+  }
+  p->n_coarse = (int64_t)p->K[0] * p->K[1] * p->K[2];
   if (nf >= 0xffffffffLL) {
     delete p;
     return DSGRFT_E_INVALID;
@@ -287,28 +337,21 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
     p->batch_cells = bu;
   }
   p->batch_units = bu;
-  p->fd = cfg->mgift;
-  if (p->fd) {
-    p->fd_np = fd_pad_length(p);
-    if (p->fd_np > 16384) {
-      delete p;
-      return DSGRFT_E_UNSUPPORTED;
-    }
-  }
 
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return DSGRFT_E_DEVICE;
   }
   size_t tot = 0;
-  const size_t f16b = (size_t)4 * p->Cp * p->Mp * 2;
+  // the GEMM-form fine tables are not built for DS-KT-MFP (FFT form only)
+  const size_t f16b = p->kt ? 0 : (size_t)4 * p->Cp * p->Mp * 2;
   p->det_ws_bytes = detect_ws_bytes(p->n_coarse * (int64_t)p->rows);
   const int64_t noise_parts = ((int64_t)M * N + 65535) / 65536;
   p->adj_ws_bytes = (size_t)(noise_parts + 64) * sizeof(double);
-  if (dalloc(&p->F32, (size_t)p->Mp * p->Cp * sizeof(float2), tot) != hipSuccess ||
+  if (dalloc(&p->F32, f16b ? (size_t)p->Mp * p->Cp * sizeof(float2) : 0, tot) != hipSuccess ||
       dalloc(&p->F16, f16b, tot) != hipSuccess ||
       dalloc(&p->FBF16, f16b, tot) != hipSuccess ||
-      dalloc(&p->F8, (size_t)4 * p->Cp * p->Mp, tot) != hipSuccess ||
+      dalloc(&p->F8, f16b ? (size_t)4 * p->Cp * p->Mp : 0, tot) != hipSuccess ||
       dalloc(&p->g_scale, (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
       (fft_form_supported(M) &&
        dalloc(&p->fft_tw, fft_table_elems(M, p->R, P) * sizeof(float2), tot) != hipSuccess) ||
@@ -316,6 +359,9 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
        (dalloc(&p->fd_tw, (size_t)p->fd_np * sizeof(float2), tot) != hipSuccess ||
         dalloc(&p->fd_spec, (size_t)M * p->fd_np * sizeof(float2), tot) != hipSuccess ||
         dalloc(&p->fd_E, (size_t)bu * M * p->rows_p * sizeof(float2), tot) != hipSuccess)) ||
+      (p->kt &&
+       (dalloc(&p->kt_spec, (size_t)M * p->fd_np * sizeof(float2), tot) != hipSuccess ||
+        dalloc(&p->kt_invd, (size_t)p->fd_np * sizeof(double), tot) != hipSuccess)) ||
       dalloc(&p->u_off, (size_t)bu * p->Mp * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->u_psi, (size_t)bu * p->Mp * sizeof(float2), tot) != hipSuccess ||
       dalloc((char **)&p->G, (size_t)bu * per_unit, tot) != hipSuccess ||
@@ -328,9 +374,10 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   }
   p->ws_bytes = tot;
   if (p->fft_tw) p->fft_chirp = p->fft_tw + M;
-  if (launch_fine_tables(p, nullptr) != hipSuccess ||
+  if ((!p->kt && launch_fine_tables(p, nullptr) != hipSuccess) ||
       (p->fft_tw && launch_fft_tables(p, nullptr) != hipSuccess) ||
       (p->fd && launch_fd_twiddles(p, nullptr) != hipSuccess) ||
+      (p->kt && launch_kt_tables(p, nullptr) != hipSuccess) ||
       hipDeviceSynchronize() != hipSuccess) {
     release(p);
     return DSGRFT_E_DEVICE;
@@ -356,6 +403,10 @@ dsgrft_status dsgrft_plan_get_info(dsgrft_plan p, dsgrft_plan_info *o) {
     o->i_lo[q] = p->ilo[q];
     o->step[q] = p->step[q];
   }
+  o->K[0] = p->gK0;
+  o->i_lo[0] = p->gilo0;
+  o->kt_q_lo = p->kt ? p->kt_q_lo : 0;
+  o->kt_folds = p->kt ? p->kt_na : 0;
   o->rows = p->rows;
   o->n_coarse = p->n_coarse;
   o->n_fine = p->n_fine;
@@ -371,6 +422,7 @@ dsgrft_status dsgrft_coarse_tables(dsgrft_plan p, int64_t cc_begin, int64_t n,
                                    int32_t *d_off, void *d_psi, void *stream) {
   if (!p || !d_off || !d_psi || n < 1 || cc_begin < 0 || cc_begin + n > p->n_coarse)
     return DSGRFT_E_INVALID;
+  if (p->kt) return DSGRFT_E_UNSUPPORTED;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   DS_TRY(launch_coarse_tables(p, cc_begin, n, p->M, d_off, (float2 *)d_psi,
                               (hipStream_t)stream));
@@ -384,12 +436,16 @@ dsgrft_status dsgrft_mgift(dsgrft_plan p, const void *d_echo, int64_t cc_begin,
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
   if (p->fd) DS_TRY(launch_range_fft(p, (const float2 *)d_echo, s));
+  if (p->kt) DS_TRY(launch_keystone(p, s));
   const GatherSrc src = gather_src(p, (const float2 *)d_echo);
   for (int64_t c0 = 0; c0 < n; c0 += p->batch_units) {
     const int64_t nc = (n - c0) < p->batch_units ? (n - c0) : p->batch_units;
     DS_TRY(launch_coarse_tables(p, cc_begin + c0, nc, p->Mp, p->u_off, p->u_psi, s,
                                 p->fd != 0));
-    if (p->fd) DS_TRY(launch_fd_shift(p, nullptr, cc_begin + c0, 0, nc, 1, s));
+    if (p->kt)
+      DS_TRY(launch_kt_shift(p, nullptr, cc_begin + c0, 0, nc, s));
+    else if (p->fd)
+      DS_TRY(launch_fd_shift(p, nullptr, cc_begin + c0, 0, nc, 1, s));
     DS_TRY(launch_mgift_out(p, src, nc,
                             (float2 *)d_out + c0 * (int64_t)p->M * p->rows, s));
   }
@@ -431,6 +487,7 @@ dsgrft_status dsgrft_grft(dsgrft_plan p, const void *d_echo, int64_t cc_begin,
   if (!d_pmax && !d_power) return DSGRFT_E_INVALID;
   if (d_power && (double)n * p->rows * (double)p->n_fine > 2147483647.0)
     return DSGRFT_E_INVALID;
+  if (p->kt) return DSGRFT_E_UNSUPPORTED;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   hipStream_t s = (hipStream_t)stream;
   const float2 *echo = (const float2 *)d_echo;
@@ -472,7 +529,7 @@ dsgrft_status dsgrft_adjoint_forward(dsgrft_plan p, const void *d_echo,
                                      const double *d_theta, int32_t B, double *d_J,
                                      double *d_saved, void *stream) {
   if (!p || !d_echo || !d_theta || !d_J || B < 1) return DSGRFT_E_INVALID;
-  if (p->P > 2) return DSGRFT_E_UNSUPPORTED;
+  if (p->P > 2 || p->kt) return DSGRFT_E_UNSUPPORTED;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   DS_TRY(launch_adjoint_forward(p, (const float2 *)d_echo, d_theta, B, d_J, d_saved,
                                 (hipStream_t)stream));
@@ -486,7 +543,7 @@ dsgrft_status dsgrft_adjoint_backward(dsgrft_plan p, const void *d_echo,
                                       void *stream) {
   if (!p || !d_echo || !d_theta || !d_saved || !d_gJ || B < 1) return DSGRFT_E_INVALID;
   if (!d_grad_theta && !d_grad_echo) return DSGRFT_E_INVALID;
-  if (p->P > 2) return DSGRFT_E_UNSUPPORTED;
+  if (p->P > 2 || p->kt) return DSGRFT_E_UNSUPPORTED;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   DS_TRY(launch_adjoint_backward(p, (const float2 *)d_echo, d_theta, B, d_saved, d_gJ,
                                  d_grad_theta, (float2 *)d_grad_echo,
@@ -498,7 +555,7 @@ dsgrft_status dsgrft_refine(dsgrft_plan p, const void *d_echo, double *d_theta,
                             int32_t B, int32_t iters, double *d_J, void *stream) {
   if (!p || !d_echo || !d_theta || !d_J || B < 1 || iters < 0 || iters > 10000)
     return DSGRFT_E_INVALID;
-  if (p->P > 2) return DSGRFT_E_UNSUPPORTED;
+  if (p->P > 2 || p->kt) return DSGRFT_E_UNSUPPORTED;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
   DS_TRY(launch_refine(p, (const float2 *)d_echo, d_theta, B, iters, d_J,
                        (hipStream_t)stream));

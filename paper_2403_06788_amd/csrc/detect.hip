@@ -72,7 +72,7 @@ __global__ __launch_bounds__(TPB) void k_det_count(const float *__restrict__ pm,
 struct PeakCtx {
   const int64_t *cells;
   int64_t cc_begin;
-  int rows, n_begin, R, P, K0, K1, K2, i0, i1, i2;
+  int rows, n_begin, R, P, K0, K1, K2, i0, i1, i2, S0;
   double dr, st0, st1, st2;
 };
 
@@ -84,8 +84,8 @@ __device__ inline dsgrft_peak make_peak(const PeakCtx &c, int64_t flat, float pw
   const int64_t k = cell_id(c.cells, c.cc_begin, pos);
   int Ks[3] = {c.K0, c.K1, c.K2}, il[3] = {c.i0, c.i1, c.i2};
   int64_t ic[3], fo[3];
-  coarse_centre(Ks, il, c.R, c.P, k, ic);
-  fine_offsets(c.R, c.P, f, fo);
+  coarse_centre(Ks, il, c.R, c.P, k, ic, c.S0);
+  fine_offsets(c.R, c.P, f, fo, c.S0);
   pk.coarse = k;
   pk.row = c.n_begin + r;
   pk.fine = f;
@@ -233,8 +233,8 @@ hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
   float *bv = (float *)(ws + 8 * ((nch * 4 + 7) / 8));
   int64_t *bi = (int64_t *)((char *)bv + 8 * ((nch * 4 + 7) / 8));
   PeakCtx ctx{cells, cc_begin, p->rows, p->n_begin, p->R, p->P, p->K[0], p->K[1],
-              p->K[2], p->ilo[0], p->ilo[1], p->ilo[2], p->dr, p->step[0],
-              p->step[1], p->step[2]};
+              p->K[2], p->ilo[0], p->ilo[1], p->ilo[2], p->S0, p->dr,
+              p->step[0], p->step[1], p->step[2]};
   hipLaunchKernelGGL(k_det_count, dim3((unsigned)nch), dim3(TPB), 0, s, pmax, total,
                      gamma2, counts, bv, bi);
   hipLaunchKernelGGL(k_det_scan, dim3(1), dim3(TPB), 0, s, counts, bv, bi, nch, pmax,

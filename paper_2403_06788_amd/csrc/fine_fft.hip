@@ -8,9 +8,12 @@
 // one inverse DFT of the de-chirped row:
 //   Y[f1, f2][n] = sum_m (G[m][n] c_f2[m]) exp(+j 2 pi f1 m / M)
 //               = X_f2[f1 mod M],   c_f2[m] = exp(+j 2 pi f2 m^2 / M^2).
-// The wanted bins are the R fine velocities [-R/2, R - R/2) taken mod M
-// (when M < R several f1 share a bin and get identical values).  Order 3
-// sits in the gathered units as in the GEMM form.
+// The wanted bins are the RV fine velocities [-HV, RV - HV) taken mod M: the
+// R fine velocities of a DS-GRFT cell (RV = R, HV = R/2; when M < R several
+// f1 share a bin and get identical values), or for DS-KT-MFP all M baseband
+// velocities i1' in [-M/2, M/2) of the folded lattice (RV = M, HV = M/2,
+// Prop. 3).  The flat fine index is f = u2 RV + u1.  Order 3 sits in the
+// gathered units as in the GEMM form.
 //
 // FFT of length M = A B (Cooley-Tukey, decimation in time): with
 // m = B m1 + m2 and output bin b = c + A d,
@@ -43,12 +46,12 @@ __device__ inline unsigned long long shfl_xor64(unsigned long long v, int m) {
 }
 
 // G: gathered batch [nunits][Mp][rows_p] complex64; chirp [R2][M]; twM [M].
-// R2 = R for P >= 2 (f2 = i2 - R/2), 1 for P = 1.
+// R2 = R for P >= 2 (f2 = i2 - R/2), 1 for P = 1; C = RV R2.
 template <int A, int B>
 __global__ __launch_bounds__(256) void k_fine_fft(
     const float2 *__restrict__ G, const float2 *__restrict__ chirp,
     const float2 *__restrict__ twM, unsigned long long *__restrict__ packed,
-    float *__restrict__ full, int Mp, int rows, int rows_p, int R, int R2,
+    float *__restrict__ full, int Mp, int rows, int rows_p, int RV, int HV, int R2,
     int64_t unit0, int R3, int C) {
   constexpr int M = A * B;
   constexpr int T = A > B ? A : B;  // threads per row
@@ -74,7 +77,6 @@ __global__ __launch_bounds__(256) void k_fine_fft(
   const int64_t ug = unit0 + u;
   const int64_t cpos = ug / R3;
   const unsigned fbase = (unsigned)((ug % R3) * C);
-  const int h = R / 2;
   unsigned long long best = 0ull;
   float2 *zrow = s_z + rl * B * ZS;
   for (int i2 = 0; i2 < R2; ++i2) {
@@ -97,9 +99,9 @@ __global__ __launch_bounds__(256) void k_fine_fft(
       for (int d = 0; d < B; ++d) {
         const int b = q + A * d;
         const float pw = y[d].x * y[d].x + y[d].y * y[d].y;
-        // fine velocity indices u1 in [0, R) with (u1 - h) = b (mod M)
-        for (int u1 = (b + h) % M; u1 < R; u1 += M) {
-          const unsigned ff = fbase + (unsigned)(i2 * R + u1);
+        // fine velocity indices u1 in [0, RV) with (u1 - HV) = b (mod M)
+        for (int u1 = (b + HV) % M; u1 < RV; u1 += M) {
+          const unsigned ff = fbase + (unsigned)(i2 * RV + u1);
           best = umax64(best, ((unsigned long long)__float_as_uint(pw) << 32) |
                                   (0xffffffffu - ff));
           if (full != nullptr && n < rows)
@@ -138,8 +140,8 @@ hipError_t launch_ab(dsgrft_plan p, int64_t nunits, int64_t unit0, float *full,
   const int R2 = p->P >= 2 ? p->R : 1;
   hipLaunchKernelGGL((k_fine_fft<A, B>), dim3((unsigned)blocks), dim3(256), 0, s,
                      (const float2 *)p->G, p->fft_chirp, p->fft_tw,
-                     p->packed, full, p->Mp, p->rows, p->rows_p, p->R, R2, unit0,
-                     p->R3, p->C);
+                     p->packed, full, p->Mp, p->rows, p->rows_p, p->S0, p->S0 / 2, R2,
+                     unit0, p->R3, p->C);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_grft(
 
   int Ks[3] = {K0, K1, K2}, il[3] = {i0, i1, i2};
   int64_t ic[3];
-  coarse_centre(Ks, il, R, P, k, ic);
+  coarse_centre(Ks, il, R, P, k, ic, R);
 
   float2 acc[FG];
 #pragma unroll
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_grft(
       float2 ph = make_float2(0.f, 0.f);
       if (f < n_fine && m < M) {
         int64_t fo[3];
-        fine_offsets(R, P, f, fo);
+        fine_offsets(R, P, f, fo, R);
         const int64_t num = lat_num(L, m, ic[0] + fo[0], ic[1] + fo[1], ic[2] + fo[2]);
         o = lat_offset(L, num);
         ph = lat_phasor(L, num);

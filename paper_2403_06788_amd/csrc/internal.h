@@ -59,7 +59,9 @@ struct dsgrft_plan_s {
   int device;
   int M, N, P, n_begin, n_end, rows;
   int R, h;
-  int K[3], ilo[3];
+  int K[3], ilo[3];     // coarse lattice the kernels walk (see S0)
+  int S0;               // axis-0 coarse step: R, or M for DS-KT-MFP
+  int gK0, gilo0;       // axis 0 of the DS-GRFT lattice (reported in the info)
   int64_t n_coarse, n_fine;
   int C;    // fine-search columns per gathered unit: R^min(P, 2)
   int R3;   // gathered units per coarse cell: R for P = 3, else 1
@@ -85,6 +87,11 @@ struct dsgrft_plan_s {
   float2 *fd_tw;        // [fd_np] exp(+j 2 pi k / fd_np)
   float2 *fd_spec;      // [M][fd_np] range spectrum of the current echo
   float2 *fd_E;         // [batch_units][M][rows_p] shifted rows
+  // DS-KT-MFP (cfg.mgift == 2; fd is 1 as well)
+  int kt;
+  int kt_q_lo, kt_na;   // folding factors q_lo .. q_lo + kt_na - 1
+  float2 *kt_spec;      // [M][fd_np] keystone-transformed spectrum
+  double *kt_invd;      // [fd_np] 1 / (R fd_np + k_s)
   unsigned long long *packed;  // [batch_cells][rows] (power bits, ~fine)
   void *det_ws;         // detection partials
   size_t det_ws_bytes;
@@ -105,23 +112,30 @@ __device__ inline int64_t cell_id(const int64_t *cells, int64_t base, int64_t i)
   return cells ? cells[i] : base + i;
 }
 
-// Coarse centre indices of cell k.
+// Coarse centre indices of cell k.  Axis 0 steps by S0 fine indices (R on
+// the DS-GRFT lattice, M on the folded velocity lattice of DS-KT-MFP, whose
+// centre q M is the folding factor), the other axes by R.
 __host__ __device__ inline void coarse_centre(const int *K, const int *ilo, int R,
-                                              int P, int64_t k, int64_t ic[3]) {
+                                              int P, int64_t k, int64_t ic[3],
+                                              int S0) {
   int64_t k1 = k % K[0];
   int64_t k2 = (k / K[0]) % K[1];
   int64_t k3 = k / ((int64_t)K[0] * K[1]);
   int64_t kk[3] = {k1, k2, k3};
-  for (int p = 0; p < 3; ++p)
-    ic[p] = (p < P) ? (int64_t)ilo[p] + kk[p] * R + R / 2 : 0;
+  for (int p = 0; p < 3; ++p) {
+    const int S = p == 0 ? S0 : R;
+    ic[p] = (p < P) ? (int64_t)ilo[p] + kk[p] * S + S / 2 : 0;
+  }
 }
 
-// Fine offsets of flat fine index f.
-__host__ __device__ inline void fine_offsets(int R, int P, int64_t f, int64_t fo[3]) {
+// Fine offsets of flat fine index f (axis 0 has S0 cells, the others R).
+__host__ __device__ inline void fine_offsets(int R, int P, int64_t f, int64_t fo[3],
+                                             int S0) {
   int64_t u = f;
   for (int p = 0; p < 3; ++p) {
-    fo[p] = (p < P) ? (u % R) - R / 2 : 0;
-    u /= R;
+    const int S = p == 0 ? S0 : R;
+    fo[p] = (p < P) ? (u % S) - S / 2 : 0;
+    u /= S;
   }
 }
 
@@ -160,6 +174,10 @@ hipError_t launch_fd_twiddles(dsgrft_plan p, hipStream_t s);
 hipError_t launch_range_fft(dsgrft_plan p, const float2 *echo, hipStream_t s);
 hipError_t launch_fd_shift(dsgrft_plan p, const int64_t *cells, int64_t cc_base,
                            int64_t unit0, int64_t nunits, int R3, hipStream_t s);
+hipError_t launch_kt_tables(dsgrft_plan p, hipStream_t s);
+hipError_t launch_keystone(dsgrft_plan p, hipStream_t s);
+hipError_t launch_kt_shift(dsgrft_plan p, const int64_t *cells, int64_t cc_base,
+                           int64_t unit0, int64_t nunits, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *ptr, int64_t n, hipStream_t s);
 hipError_t launch_fine_f32(dsgrft_plan p, int64_t nunits, int64_t unit0,
                            float *full, int64_t full_cell0, hipStream_t s);

@@ -18,105 +18,17 @@
 // The rows E[u] then go through the ordinary gathers with zero offsets, which
 // apply the pre-DFM phase (eq. (47)) and write the fine search's layout.
 //
-// Both transforms are Stockham autosort FFTs in LDS, one workgroup of 256
-// threads per row: pass with span NS and radix R reads X[j + t NP/R], scales
-// by W^(t (j mod NS)), runs an R-point FFT in registers and writes
-// X[(j/NS) NS R + (j mod NS) + t NS].  Every thread loads all its groups
-// before the barrier and writes after it, so the pass works in place.  The
-// radices are 16 with the remainder folded into the first pass (32 or 64) or
-// a last pass of 4 or 8, so NP = 8192 takes three passes.  Twiddles come from
-// two small LDS tables, W^i = TH[i >> 7] TL[i & 127].
-#include "fft_reg.h"
+// Both transforms are the LDS Stockham FFTs of fft_lds.h, one workgroup of
+// 256 threads per row.
+#include "fft_lds.h"
 #include "internal.h"
 
 namespace {
 
 using fftreg::cmulf;
-using fftreg::fft_reg;
-
-__device__ inline float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
-
-// Twiddle W^i = exp(+j 2 pi i / NP) from the two LDS tables.
-struct TwLds {
-  const float2 *lo;  // [128] W^i
-  const float2 *hi;  // [NP / 128] W^(128 i)
-  __device__ float2 operator()(int i) const { return cmulf(hi[i >> 7], lo[i & 127]); }
-};
-
-// One Stockham pass; INV selects the sign.
-template <int NP, int NS, int R, bool INV>
-__device__ inline void stockham_pass(float2 *X, const TwLds &tw) {
-  constexpr int NG = NP / R;
-  constexpr int GPT = (NG + 255) / 256;
-  const int tid = threadIdx.x;
-  float2 v[GPT][R];
-#pragma unroll
-  for (int g = 0; g < GPT; ++g) {
-    const int j = tid + 256 * g;
-    if (j < NG) {
-      const int k = j % NS;
-#pragma unroll
-      for (int t = 0; t < R; ++t) {
-        float2 x = X[j + t * NG];
-        if (NS > 1 && t > 0) {
-          const float2 w = tw(t * k * (NP / (NS * R)));
-          x = cmulf(x, INV ? w : conjf2(w));
-        }
-        v[g][t] = x;
-      }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int g = 0; g < GPT; ++g) {
-    const int j = tid + 256 * g;
-    if (j < NG) {
-      const int k = j % NS;
-      if (!INV) {
-#pragma unroll
-        for (int t = 0; t < R; ++t) v[g][t] = conjf2(v[g][t]);
-      }
-      fft_reg<R>(v[g]);
-      const int d = (j / NS) * NS * R + k;
-#pragma unroll
-      for (int t = 0; t < R; ++t) X[d + t * NS] = INV ? v[g][t] : conjf2(v[g][t]);
-    }
-  }
-  __syncthreads();
-}
-
-// Radix of the pass with span NS: NP = 16^q r; r = 2 (or 4 for NP >= 16384)
-// joins the first pass (32, 64), otherwise r is a last pass (4, 8).
-template <int NP, int NS>
-constexpr int pass_radix() {
-  int e = 0;
-  while ((1 << e) < NP) ++e;
-  const int rem = e % 4;
-  if (NS == 1 && e >= 5 && (rem == 1 || (rem == 2 && NP >= 16384))) return 16 << rem;
-  const int left = NP / NS;
-  return left % 16 == 0 ? 16 : left;
-}
-
-template <int NP, int NS, bool INV>
-__device__ inline void fft_lds(float2 *X, const TwLds &tw) {
-  if constexpr (NS < NP) {
-    constexpr int R = pass_radix<NP, NS>();
-    static_assert(NP % (NS * R) == 0, "radix plan");
-    stockham_pass<NP, NS, R, INV>(X, tw);
-    fft_lds<NP, NS * R, INV>(X, tw);
-  }
-}
-
-// Fill the two twiddle tables from the global W table.
-template <int NP>
-__device__ inline TwLds load_twiddles(const float2 *__restrict__ tw, float2 *lo, float2 *hi) {
-  constexpr int NH = NP / 128 > 1 ? NP / 128 : 1;
-  for (int i = threadIdx.x; i < 128 + NH; i += 256) {
-    if (i < 128) lo[i] = tw[i % NP];
-    else hi[i - 128] = tw[((i - 128) * 128) % NP];
-  }
-  return TwLds{lo, hi};
-}
+using fftlds::TwLds;
+using fftlds::fft_lds;
+using fftlds::load_twiddles;
 
 template <int NP>
 __global__ __launch_bounds__(256) void k_range_fft(const float2 *__restrict__ echo,
@@ -152,7 +64,7 @@ __global__ __launch_bounds__(256) void k_fd_shift(
   const int64_t k = cell_id(cells, cc_base, cpos);
   const int Ks[3] = {K0, K1, K2}, il[3] = {i0, i1, i2};
   int64_t ic[3];
-  coarse_centre(Ks, il, R, P, k, ic);
+  coarse_centre(Ks, il, R, P, k, ic, R);
   const int64_t num = lat_num(L, m, ic[0], ic[1], ic[2]);
   const int64_t xi = floor_div(num, L.RM3);
   const double xf = (double)(num - xi * L.RM3) / (double)L.RM3;

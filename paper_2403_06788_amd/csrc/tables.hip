@@ -95,8 +95,8 @@ __global__ void k_fine_tables(int M, int Mp, int C, int Cp, int R, int P, Lat L,
 __global__ void k_unit_tables(const int64_t *cells, int64_t cc_base,
                               int64_t unit0, int64_t nunits, int M, int Mp,
                               int R3, int R, int P, int K0, int K1, int K2,
-                              int i0, int i1, int i2, Lat L, int zero_off,
-                              int32_t *off, float2 *psi) {
+                              int i0, int i1, int i2, int S0, Lat L,
+                              int zero_off, int32_t *off, float2 *psi) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nunits * Mp) return;
   int64_t u = t / Mp;
@@ -109,7 +109,7 @@ __global__ void k_unit_tables(const int64_t *cells, int64_t cc_base,
     int64_t k = cell_id(cells, cc_base, cpos);
     int Ks[3] = {K0, K1, K2}, il[3] = {i0, i1, i2};
     int64_t ic[3];
-    coarse_centre(Ks, il, R, P, k, ic);
+    coarse_centre(Ks, il, R, P, k, ic, S0);
     int64_t num_c = lat_num(L, m, ic[0], ic[1], ic[2]);
     o = zero_off ? 0 : lat_offset(L, num_c);
     int64_t f3 = (P == 3) ? (u3 - R / 2) : 0;
@@ -121,8 +121,8 @@ __global__ void k_unit_tables(const int64_t *cells, int64_t cc_base,
 
 __global__ void k_coarse_tables(int64_t cc_begin, int64_t n, int M, int stride,
                                 int R, int P, int K0, int K1, int K2, int i0,
-                                int i1, int i2, Lat L, int zero_off, int32_t *off,
-                                float2 *psi) {
+                                int i1, int i2, int S0, Lat L, int zero_off,
+                                int32_t *off, float2 *psi) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * M) return;
   int64_t i = t / M;
@@ -130,7 +130,7 @@ __global__ void k_coarse_tables(int64_t cc_begin, int64_t n, int M, int stride,
   int m = (int)(t % M);
   int Ks[3] = {K0, K1, K2}, il[3] = {i0, i1, i2};
   int64_t ic[3];
-  coarse_centre(Ks, il, R, P, k, ic);
+  coarse_centre(Ks, il, R, P, k, ic, S0);
   int64_t num = lat_num(L, m, ic[0], ic[1], ic[2]);
   off[i * stride + m] = zero_off ? 0 : lat_offset(L, num);
   psi[i * stride + m] = lat_phasor(L, num);
@@ -156,7 +156,7 @@ hipError_t launch_unit_tables(dsgrft_plan p, const int64_t *cells,
   hipLaunchKernelGGL(k_unit_tables, dim3(blocks(n, 256)), dim3(256), 0, s,
                      cells, cc_base, unit0, nunits, p->M, p->Mp, p->R3, p->R,
                      p->P, p->K[0], p->K[1], p->K[2], p->ilo[0], p->ilo[1],
-                     p->ilo[2], p->lat, p->fd, p->u_off, p->u_psi);
+                     p->ilo[2], p->S0, p->lat, p->fd, p->u_off, p->u_psi);
   return hipGetLastError();
 }
 
@@ -166,6 +166,7 @@ hipError_t launch_coarse_tables(dsgrft_plan p, int64_t cc_begin, int64_t n,
   int64_t tot = n * p->M;
   hipLaunchKernelGGL(k_coarse_tables, dim3(blocks(tot, 256)), dim3(256), 0, s,
                      cc_begin, n, p->M, stride, p->R, p->P, p->K[0], p->K[1], p->K[2],
-                     p->ilo[0], p->ilo[1], p->ilo[2], p->lat, zero_off ? 1 : 0, off, psi);
+                     p->ilo[0], p->ilo[1], p->ilo[2], p->S0, p->lat, zero_off ? 1 : 0,
+                     off, psi);
   return hipGetLastError();
 }

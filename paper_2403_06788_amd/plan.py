@@ -37,8 +37,10 @@ class Plan:
     fc, fs, prf: carrier [Hz], range sampling rate [Hz], PRF [Hz];
     axes: [(vmin, vmax), (amin, amax), (jmin, jmax)][:order];
     rows: optional (n_begin, n_end) range rows of interest;
-    mgift: "td" (nearest-bin gather along the coarse walk) or "fd"
-    (frequency-domain coarse compensation of Alg. 1).
+    mgift: "td" (nearest-bin gather along the coarse walk), "fd"
+    (frequency-domain coarse compensation of Alg. 1) or "kt" (DS-KT-MFP,
+    Alg. 4: keystone transform and folded velocity lattice; order 2, FFT
+    form only).
     """
 
     def __init__(self, fc, fs, prf, M, N, order, axes, rows=None, c=3.0e8,
@@ -51,9 +53,10 @@ class Plan:
         for p, ax in enumerate(axes):
             cfg.axis[p].min, cfg.axis[p].max = float(ax[0]), float(ax[1])
         cfg.batch = batch
-        if mgift not in ("td", "fd"):
-            raise ValueError('mgift must be "td" or "fd"')
-        cfg.mgift = 1 if mgift == "fd" else 0
+        modes = {"td": 0, "fd": 1, "kt": 2}
+        if mgift not in modes:
+            raise ValueError('mgift must be "td", "fd" or "kt"')
+        cfg.mgift = modes[mgift]
         h = C.c_void_p()
         check("dsgrft_plan_create", L.dsgrft_plan_create(C.byref(radar), C.byref(cfg), C.byref(h)))
         self._h = h
@@ -72,6 +75,7 @@ class Plan:
         self.step = tuple(info.step)
         self.workspace_bytes = info.workspace_bytes
         self.fd_pad = info.fd_pad
+        self.kt_q_lo, self.kt_folds = info.kt_q_lo, info.kt_folds
         self.prf = prf
         self.mgift_mode = mgift
 
