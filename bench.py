@@ -529,7 +529,7 @@ def bench_kt(args):
                       "cells": cells * plan.rows * plan.n_fine, "pulses": plan.M},
            "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": peak,
                         "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                        "kernel": "k_fine_fft<32, 32>",
+                        "kernel": f"k_fine_fft_w<{plan.M // 64}, full bins>",
                         "avg_launch_ms": round(fine_avg_s * 1e3, 4),
                         "flops_per_launch": flops_launch, "launches": prof["fine_launches"]},
            "gather_ms_per_step": round(prof["gather_ms"] / args.steps, 3),

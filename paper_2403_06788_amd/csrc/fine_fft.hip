@@ -116,6 +116,126 @@ __global__ __launch_bounds__(256) void k_fine_fft(
   if (q == 0 && n < rows) atomicMax(&packed[cpos * rows + n], best);
 }
 
+// Orders LDS accesses of one wavefront: its lanes exchange data through a
+// private LDS region, and LDS operations of a wavefront complete in order, so
+// a wavefront-scope fence is all the ordering needed (no workgroup barrier).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wavefront-per-row form for M = 64 P (P = 8, 16, 32): each wavefront owns a
+// range row, each lane P of its pulses.  With m = 64 a + l (lane l) and
+// output bin k = k1 + P (k2a + 8 k2b),
+//   X[k] = sum_l2 W_8^(l2 k2b) W_64^(l2 k2a)
+//            sum_l1 W_8^(l1 k2a) W_M^(l k1) sum_a x[64 a + l] W_P^(a k1),
+// l = 8 l1 + l2: pass 1 is a P-point FFT over a in the lane's registers
+// followed by the twiddles W_M^(l k1) (from LDS); pass 2, on lane 8 kq + l2,
+// the 8-point FFTs over l1 for k1 = kq + 8 j and the twiddles W_64^(l2 k2a);
+// pass 3, on lane 8 kq + k2a, the 8-point FFTs over l2.  The two exchanges go
+// through the wavefront's LDS rows: exchange 1 puts Z[l][k1] in row
+// 8 (k1 / 8) + l / 8 (length 72) at 8 (k1 % 8) + l % 8, exchange 2 puts
+// V[k1][l2][k2a] in row 8 j + k2a (length 65) at 8 kq + l2; every access of
+// both is conflict-free (contiguous on one side, padded rows on the other).
+// FULL (RV = M, HV = M/2) maps bin k to u1 = k xor M/2 without a range test.
+template <int P, int NW, bool FULL>
+__global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
+    const float2 *__restrict__ G, const float2 *__restrict__ chirp,
+    const float2 *__restrict__ twM, unsigned long long *__restrict__ packed,
+    float *__restrict__ full, int Mp, int rows, int rows_p, int RV, int HV, int R2,
+    int64_t unit0, int R3, int C) {
+  constexpr int M = 64 * P;
+  constexpr int NJ = P / 8;
+  constexpr int ROW1 = 72, ROW2 = 65;
+  constexpr int XS = P * ROW1;
+  static_assert(P % 8 == 0 && P <= 32, "points per lane");
+  __shared__ float2 s_tw[M];            // [k1][l] = W_M^(l k1)
+  __shared__ float2 s_x[NW * XS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int bpu = rows_p / NW;
+  const int64_t u = blockIdx.x / bpu;
+  const int n = (int)(blockIdx.x % bpu) * NW + w;
+  for (int i = tid; i < M; i += 64 * NW) s_tw[i] = twM[((i & 63) * (i >> 6)) & (M - 1)];
+  float2 g[P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) g[a] = G[((int64_t)u * Mp + 64 * a + lane) * rows_p + n];
+  // W_64^(l2 k2a) for this lane's l2 in pass 2
+  float2 t2[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) t2[k] = twM[(P * (lane & 7) * k) & (M - 1)];
+  __syncthreads();
+
+  const int64_t ug = unit0 + u;
+  const int64_t cpos = ug / R3;
+  const unsigned fbase = (unsigned)((ug % R3) * C);
+  float2 *xb = s_x + w * XS;
+  const int kq = lane >> 3, lo3 = lane & 7;
+  unsigned long long best = 0ull;
+  for (int i2 = 0; i2 < R2; ++i2) {
+    const float2 *ch = chirp + (int64_t)i2 * M;
+    float2 x[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) x[a] = cmulf(g[a], ch[64 * a + lane]);
+    fft_reg<P>(x);
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      const float2 z = k1 ? cmulf(x[k1], s_tw[k1 * 64 + lane]) : x[0];
+      xb[((k1 >> 3) * 8 + kq) * ROW1 + 8 * (k1 & 7) + lo3] = z;
+    }
+    wave_lds_sync();
+    float2 v[NJ][8];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+      for (int l1 = 0; l1 < 8; ++l1) v[j][l1] = xb[(j * 8 + l1) * ROW1 + lane];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      fft_reg<8>(v[j]);
+#pragma unroll
+      for (int k = 1; k < 8; ++k) v[j][k] = cmulf(v[j][k], t2[k]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) xb[(j * 8 + k) * ROW2 + lane] = v[j][k];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+      for (int l2 = 0; l2 < 8; ++l2) v[j][l2] = xb[(j * 8 + lo3) * ROW2 + 8 * kq + l2];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      fft_reg<8>(v[j]);
+#pragma unroll
+      for (int k2b = 0; k2b < 8; ++k2b) {
+        const int b = kq + 8 * j + P * (lo3 + 8 * k2b);
+        const float pw = v[j][k2b].x * v[j][k2b].x + v[j][k2b].y * v[j][k2b].y;
+        if (FULL) {
+          const unsigned ff = fbase + (unsigned)(i2 * M + (b ^ (M / 2)));
+          best = umax64(best, ((unsigned long long)__float_as_uint(pw) << 32) |
+                                  (0xffffffffu - ff));
+          if (full != nullptr && n < rows)
+            full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pw;
+        } else {
+          for (int u1 = (b + HV) % M; u1 < RV; u1 += M) {
+            const unsigned ff = fbase + (unsigned)(i2 * RV + u1);
+            best = umax64(best, ((unsigned long long)__float_as_uint(pw) << 32) |
+                                    (0xffffffffu - ff));
+            if (full != nullptr && n < rows)
+              full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pw;
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) best = umax64(best, shfl_xor64(best, s));
+  if (lane == 0 && n < rows) atomicMax(&packed[cpos * rows + n], best);
+}
+
 __global__ void k_fft_tables(int M, int R, int R2, int P, Lat L, float2 *twM,
                              float2 *chirp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -145,6 +265,23 @@ hipError_t launch_ab(dsgrft_plan p, int64_t nunits, int64_t unit0, float *full,
   return hipGetLastError();
 }
 
+template <int P, int NW>
+hipError_t launch_w(dsgrft_plan p, int64_t nunits, int64_t unit0, float *full,
+                    hipStream_t s) {
+  const int64_t blocks = nunits * (p->rows_p / NW);
+  const int R2 = p->P >= 2 ? p->R : 1;
+  const bool fullbins = p->S0 == p->M;
+  if (fullbins)
+    hipLaunchKernelGGL((k_fine_fft_w<P, NW, true>), dim3((unsigned)blocks), dim3(64 * NW), 0,
+                       s, (const float2 *)p->G, p->fft_chirp, p->fft_tw, p->packed, full,
+                       p->Mp, p->rows, p->rows_p, p->S0, p->S0 / 2, R2, unit0, p->R3, p->C);
+  else
+    hipLaunchKernelGGL((k_fine_fft_w<P, NW, false>), dim3((unsigned)blocks), dim3(64 * NW), 0,
+                       s, (const float2 *)p->G, p->fft_chirp, p->fft_tw, p->packed, full,
+                       p->Mp, p->rows, p->rows_p, p->S0, p->S0 / 2, R2, unit0, p->R3, p->C);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 bool fft_form_supported(int M) {
@@ -169,9 +306,9 @@ hipError_t launch_fine_fft(dsgrft_plan p, int64_t nunits, int64_t unit0,
     case 64: return launch_ab<8, 8>(p, nunits, unit0, full, s);
     case 128: return launch_ab<16, 8>(p, nunits, unit0, full, s);
     case 256: return launch_ab<16, 16>(p, nunits, unit0, full, s);
-    case 512: return launch_ab<32, 16>(p, nunits, unit0, full, s);
-    case 1024: return launch_ab<32, 32>(p, nunits, unit0, full, s);
-    case 2048: return launch_ab<32, 64>(p, nunits, unit0, full, s);
+    case 512: return launch_w<8, 4>(p, nunits, unit0, full, s);
+    case 1024: return launch_w<16, 4>(p, nunits, unit0, full, s);
+    case 2048: return launch_w<32, 2>(p, nunits, unit0, full, s);
     default: return hipErrorInvalidValue;
   }
 }
