@@ -181,15 +181,23 @@ def main():
     peaks, count, best = plan.detect(pm, af, gamma2, cap=4096)
 
     fine_avg_s = prof["fine_ms"] / max(prof["fine_launches"], 1) * 1e-3
-    fine_flops_launch = prof["fine_flops"] / max(prof["fine_launches"], 1)
+    fft = args.form == "f32fft"
+    if fft:
+        # FFT form: R de-chirped M-point FFTs per (unit, row), not 8 flops
+        # per cell-pulse
+        fine_flops_launch = prof["fine_cell_pulses"] / max(prof["fine_launches"], 1) \
+            / (plan.M * plan.R * plan.R) * plan.R * fft_flops(plan.M)
+    else:
+        fine_flops_launch = prof["fine_flops"] / max(prof["fine_launches"], 1)
     achieved = fine_flops_launch / fine_avg_s / 1e12
     peak = PEAK_TFLOPS[args.form]
     gather_avg_s = prof["gather_ms"] / max(prof["gather_launches"], 1) * 1e-3
     gather_bytes = prof["gather_bytes"] / max(prof["gather_launches"], 1)
-    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": recorded_traffic(args.form, args.split),
-                "kernel": f"k_fine_mfma<{args.form}, split {args.split}>",
+    roofline = {"bound": "alu" if fft else "mfma", "achieved": round(achieved, 2),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": None if fft else recorded_traffic(args.form, args.split),
+                "kernel": f"k_fine_fft_w<{plan.M // 64}>" if fft
+                          else f"k_fine_mfma<{args.form}, split {args.split}>",
                 "avg_launch_ms": round(fine_avg_s * 1e3, 4),
                 "flops_per_launch": fine_flops_launch,
                 "launches": prof["fine_launches"]}
@@ -542,15 +550,30 @@ def bench_kt(args):
 
 
 PD_PFA = 1e-8          # per-cell false-alarm probability of the LRT threshold
-PD_DETECTORS = ("ds_td", "ds_fd", "grft")
+PD_DETECTORS = ("ds_td", "ds_fd", "ds_kt", "grft")
+
+
+def kt_cell(plan, v, a):
+    """DS-KT-MFP coarse cell (folding factor, coarse acceleration) holding
+    the nearest lattice point of (v, a)."""
+    import numpy as np
+    i1 = int(np.floor(v / plan.step[0] + 0.5))
+    q = (i1 + plan.M // 2) // plan.M - plan.kt_q_lo
+    q = min(max(q, 0), plan.kt_folds - 1)
+    k2 = int(np.floor((a / plan.step[1] - plan.i_lo[1] + 0.5) / plan.R))
+    k2 = min(max(k2, 0), plan.K[1] - 1)
+    return k2 * plan.kt_folds + q
 
 
 def pd_trial(plans, echo, target, gamma2):
     """Detection statistics of one trial: for each detector, the largest
     reduced power over the target's coarse cell and its two neighbours along
-    v, in range rows round(r0 / dr) +- 2, and whether it exceeds gamma2.
-    DS-GRFT uses the f16 MFMA form; the single-scale TD-GRFT runs in FP32."""
+    v (DS-KT-MFP: the target's folding-factor cell, M R fine cells), in range
+    rows round(r0 / dr) +- 2, and whether it exceeds gamma2.  DS-GRFT uses
+    the f16 MFMA form, DS-KT-MFP the FFT form; the single-scale TD-GRFT runs
+    in FP32."""
     import numpy as np
+    import torch
     p = plans["ds_td"]
     ks = []
     for q, val in enumerate((target.v, target.a)):
@@ -562,21 +585,25 @@ def pd_trial(plans, echo, target, gamma2):
     rb = int(round(target.r0 / p.dr))
     r0, r1 = max(0, rb - 2), min(p.rows, rb + 3)
     out = {}
+    ktc = kt_cell(plans["ds_kt"], target.v, target.a)
     for name in PD_DETECTORS:
         if name == "grft":
             pm, _ = p.grft(echo, cells[0], len(cells))
+        elif name == "ds_kt":
+            pm, _ = plans[name].search(echo, "f32fft", 1,
+                                       cells=torch.tensor([ktc], dtype=torch.int64))
         else:
             pm, _ = plans[name].search(echo, "f16", 1, cc_begin=cells[0], n=len(cells))
         stat = float(pm[:, r0:r1].max())
         out[name] = (stat, stat > gamma2)
-    return out, cells, (r0, r1), kt
+    return out, cells, (r0, r1), kt, ktc
 
 
 def bench_pd(args):
     """Monte-Carlo detection probability vs per-pulse SNR (the shape of the
     paper's Exp. 2): one random target per trial (uniform r0, v, a), sigma^2 = 1
     noise, LRT threshold at P_FA = 1e-8 per cell, for DS-GRFT with the
-    time-domain gather, DS-GRFT with the frequency-domain mGIFT and
+    time-domain gather, DS-GRFT with the frequency-domain mGIFT, DS-KT-MFP and
     single-scale TD-GRFT; noise-only trials give the false-alarm rate of the
     neighbourhood test."""
     import numpy as np
@@ -588,7 +615,9 @@ def bench_pd(args):
     r = sc["radar"]
     plans = {"ds_td": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"]),
              "ds_fd": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"],
-                           mgift="fd")}
+                           mgift="fd"),
+             "ds_kt": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"],
+                           mgift="kt")}
     gamma2 = plans["ds_td"].threshold(1.0, PD_PFA)
     rng = np.random.Generator(np.random.PCG64(2406))
     snrs = [None] + [float(x) for x in np.arange(-16.0, -3.9, 1.0)]
@@ -603,7 +632,7 @@ def bench_pd(args):
                                     sc["v"], sc["a"], sc["j"])[0]
             echo_np = synth.make_echo(r, sc["M"], sc["N"], [] if snr is None else [tg], 1.0, rng)
             echo = torch.from_numpy(echo_np).cuda()
-            res, _, _, _ = pd_trial(plans, echo, tg, gamma2)
+            res = pd_trial(plans, echo, tg, gamma2)[0]
             for d in PD_DETECTORS:
                 hits[d] += int(res[d][1])
             n_trials += 1
@@ -623,7 +652,7 @@ def bench_pd(args):
     loss = None
     if at["ds_td"]["pd_0.9"] is not None and at["ds_fd"]["pd_0.9"] is not None:
         loss = at["ds_td"]["pd_0.9"] - at["ds_fd"]["pd_0.9"]
-    out = {"metric": "Monte-Carlo trials/s (3 detectors, M=256)", "value": n_trials / dt,
+    out = {"metric": "Monte-Carlo trials/s (4 detectors, M=256)", "value": n_trials / dt,
            "unit": "trials/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "vs_baseline": None,
            "config": {"workload": "Pd vs per-pulse SNR, M=256 pulses, N=512 bins, P=2, "

@@ -6,8 +6,10 @@
 
 namespace fftreg {
 
+// Complex product with its fused multiply-adds written out, so that the
+// rounding does not depend on how the compiler contracts the surrounding code.
 __device__ inline float2 cmulf(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 
 __host__ __device__ constexpr int bitrev(int i, int n) {
@@ -81,6 +83,30 @@ __device__ inline float2 twiddle(float2 x, int idx) {
   }
 }
 
+// Butterfly a +- x exp(+j 2 pi idx / 64).  For the factors exp(+-j pi/4),
+// exp(+-j 3pi/4) the scaling by sqrt(1/2) is fused into the additions; every
+// fused operation is written out (fmaf), none is left to the compiler.
+__device__ inline void butterfly(float2 &a, float2 &x, int idx) {
+  constexpr float h = 0.70710678118654752f;  // sqrt(1/2)
+  float s1, s2, c1, c2;                       // b = (c1 h s1, c2 h s2)
+  switch (idx) {
+    case 8: s1 = x.x - x.y; s2 = x.x + x.y; c1 = h; c2 = h; break;
+    case 24: s1 = x.x + x.y; s2 = x.x - x.y; c1 = -h; c2 = h; break;
+    case 40: s1 = x.y - x.x; s2 = x.x + x.y; c1 = h; c2 = -h; break;
+    case 56: s1 = x.x + x.y; s2 = x.y - x.x; c1 = h; c2 = h; break;
+    default: {
+      const float2 b = twiddle(x, idx);
+      const float2 t = a;
+      a = make_float2(t.x + b.x, t.y + b.y);
+      x = make_float2(t.x - b.x, t.y - b.y);
+      return;
+    }
+  }
+  const float2 t = a;
+  a = make_float2(fmaf(c1, s1, t.x), fmaf(c2, s2, t.y));
+  x = make_float2(fmaf(-c1, s1, t.x), fmaf(-c2, s2, t.y));
+}
+
 // In-register radix-2 FFT, N a power of two <= 64, positive exponent:
 // x[k] <- sum_j x[j] exp(+j 2 pi j k / N), natural order in and out.
 template <int N>
@@ -99,12 +125,7 @@ __device__ inline void fft_reg(float2 (&x)[N]) {
 #pragma unroll
     for (int i = 0; i < N; i += len) {
 #pragma unroll
-      for (int k = 0; k < len / 2; ++k) {
-        const float2 a = x[i + k];
-        const float2 b = twiddle(x[i + k + len / 2], k * (64 / len));
-        x[i + k] = make_float2(a.x + b.x, a.y + b.y);
-        x[i + k + len / 2] = make_float2(a.x - b.x, a.y - b.y);
-      }
+      for (int k = 0; k < len / 2; ++k) butterfly(x[i + k], x[i + k + len / 2], k * (64 / len));
     }
   }
 }

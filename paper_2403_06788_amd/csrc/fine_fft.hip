@@ -25,6 +25,10 @@
 // row's gathered samples stay in registers for all R chirps, and each thread
 // keeps its best (power, -fine) key, merged per row at the end with the same
 // 64-bit atomicMax as the GEMM form (ties to the smaller fine index).
+// No implicit contraction in this file: the full-map and reduced-map variants
+// of a kernel must round identically, so every fused multiply-add is explicit.
+#pragma clang fp contract(off)
+
 #include "fft_reg.h"
 #include "internal.h"
 
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(256) void k_fine_fft(
 #pragma unroll
       for (int d = 0; d < B; ++d) {
         const int b = q + A * d;
-        const float pw = y[d].x * y[d].x + y[d].y * y[d].y;
+        const float pw = fmaf(y[d].x, y[d].x, y[d].y * y[d].y);
         // fine velocity indices u1 in [0, RV) with (u1 - HV) = b (mod M)
         for (int u1 = (b + HV) % M; u1 < RV; u1 += M) {
           const unsigned ff = fbase + (unsigned)(i2 * RV + u1);
@@ -138,8 +142,9 @@ __device__ inline void wave_lds_sync() {
 // 8 (k1 / 8) + l / 8 (length 72) at 8 (k1 % 8) + l % 8, exchange 2 puts
 // V[k1][l2][k2a] in row 8 j + k2a (length 65) at 8 kq + l2; every access of
 // both is conflict-free (contiguous on one side, padded rows on the other).
-// FULL (RV = M, HV = M/2) maps bin k to u1 = k xor M/2 without a range test.
-template <int P, int NW, bool FULL>
+// FULL (RV = M, HV = M/2) maps bin k to u1 = k xor M/2 (one fine index per
+// bin, no range test).
+template <int P, int NW, bool FULL, bool WFULL>
 __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
     const float2 *__restrict__ G, const float2 *__restrict__ chirp,
     const float2 *__restrict__ twM, unsigned long long *__restrict__ packed,
@@ -171,8 +176,31 @@ __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
   const unsigned fbase = (unsigned)((ug % R3) * C);
   float2 *xb = s_x + w * XS;
   const int kq = lane >> 3, lo3 = lane & 7;
+  // Fast argmax: each lane keeps its largest power over the wanted bins and
+  // the first chirp reaching it; after the last chirp the wavefront takes the
+  // best (power, smallest chirp) and runs that chirp once more through the
+  // same loop body with the exact per-bin keys (power bits, ~fine index), so
+  // ties still go to the smaller fine index.  The full-map variant (WFULL)
+  // and short chirp counts use the per-bin keys on every chirp.
+  if (FULL) {
+    RV = M;
+    HV = M / 2;
+  }
+  const bool direct = WFULL || R2 < 4;
+  float bp = 0.f;
+  int bi = 0;
   unsigned long long best = 0ull;
-  for (int i2 = 0; i2 < R2; ++i2) {
+  const int iters = direct ? R2 : R2 + 1;
+  for (int it = 0; it < iters; ++it) {
+    const bool fin = !direct && it == R2;
+    int i2 = it;
+    if (fin) {
+      unsigned long long kb = ((unsigned long long)__float_as_uint(bp) << 32) |
+                              (0xffffffffu - (unsigned)bi);
+#pragma unroll
+      for (int s = 1; s < 64; s <<= 1) kb = umax64(kb, shfl_xor64(kb, s));
+      i2 = __builtin_amdgcn_readfirstlane((int)(0xffffffffu - (unsigned)kb));
+    }
     const float2 *ch = chirp + (int64_t)i2 * M;
     float2 x[P];
 #pragma unroll
@@ -207,25 +235,38 @@ __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
     }
     wave_lds_sync();
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      fft_reg<8>(v[j]);
+    for (int j = 0; j < NJ; ++j) fft_reg<8>(v[j]);
+    if (!direct && !fin) {
+      float cm = 0.f;
 #pragma unroll
-      for (int k2b = 0; k2b < 8; ++k2b) {
-        const int b = kq + 8 * j + P * (lo3 + 8 * k2b);
-        const float pw = v[j][k2b].x * v[j][k2b].x + v[j][k2b].y * v[j][k2b].y;
-        if (FULL) {
-          const unsigned ff = fbase + (unsigned)(i2 * M + (b ^ (M / 2)));
-          best = umax64(best, ((unsigned long long)__float_as_uint(pw) << 32) |
-                                  (0xffffffffu - ff));
-          if (full != nullptr && n < rows)
-            full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pw;
-        } else {
-          for (int u1 = (b + HV) % M; u1 < RV; u1 += M) {
+      for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+        for (int k2b = 0; k2b < 8; ++k2b) {
+          const float pw = fmaf(v[j][k2b].x, v[j][k2b].x, v[j][k2b].y * v[j][k2b].y);
+          if (FULL) {
+            cm = fmaxf(cm, pw);
+          } else {
+            const int b = kq + 8 * j + P * (lo3 + 8 * k2b);
+            cm = ((b + HV) % M < RV) ? fmaxf(cm, pw) : cm;
+          }
+        }
+      }
+      if (cm > bp) {
+        bp = cm;
+        bi = i2;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+        for (int k2b = 0; k2b < 8; ++k2b) {
+          const int b = kq + 8 * j + P * (lo3 + 8 * k2b);
+          const float pw = fmaf(v[j][k2b].x, v[j][k2b].x, v[j][k2b].y * v[j][k2b].y);
+          for (int u1 = FULL ? (b ^ (M / 2)) : (b + HV) % M; u1 < RV; u1 += M) {
             const unsigned ff = fbase + (unsigned)(i2 * RV + u1);
             best = umax64(best, ((unsigned long long)__float_as_uint(pw) << 32) |
                                     (0xffffffffu - ff));
-            if (full != nullptr && n < rows)
-              full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pw;
+            if (WFULL && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pw;
           }
         }
       }
@@ -271,14 +312,11 @@ hipError_t launch_w(dsgrft_plan p, int64_t nunits, int64_t unit0, float *full,
   const int64_t blocks = nunits * (p->rows_p / NW);
   const int R2 = p->P >= 2 ? p->R : 1;
   const bool fullbins = p->S0 == p->M;
-  if (fullbins)
-    hipLaunchKernelGGL((k_fine_fft_w<P, NW, true>), dim3((unsigned)blocks), dim3(64 * NW), 0,
-                       s, (const float2 *)p->G, p->fft_chirp, p->fft_tw, p->packed, full,
-                       p->Mp, p->rows, p->rows_p, p->S0, p->S0 / 2, R2, unit0, p->R3, p->C);
-  else
-    hipLaunchKernelGGL((k_fine_fft_w<P, NW, false>), dim3((unsigned)blocks), dim3(64 * NW), 0,
-                       s, (const float2 *)p->G, p->fft_chirp, p->fft_tw, p->packed, full,
-                       p->Mp, p->rows, p->rows_p, p->S0, p->S0 / 2, R2, unit0, p->R3, p->C);
+  auto kern = fullbins ? (full ? k_fine_fft_w<P, NW, true, true> : k_fine_fft_w<P, NW, true, false>)
+                       : (full ? k_fine_fft_w<P, NW, false, true> : k_fine_fft_w<P, NW, false, false>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NW), 0, s, (const float2 *)p->G,
+                     p->fft_chirp, p->fft_tw, p->packed, full, p->Mp, p->rows, p->rows_p,
+                     p->S0, p->S0 / 2, R2, unit0, p->R3, p->C);
   return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ import torch
 
 import synth
 from oracle import fd as OF
+from oracle import ktmfp as KT
 from oracle import transforms as OT
 from oracle.grid import Axis, Radar, make_grid
 
@@ -21,7 +22,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 
-def _oracle_stats(echo, grid, cells, rows):
+def _oracle_stats(echo, grid, cells, rows, ktc):
     r = np.arange(*rows)
     F = OT.fine_matrix(grid)
     Np = OF.pad_length(grid)
@@ -32,7 +33,9 @@ def _oracle_stats(echo, grid, cells, rows):
               for k in cells)
     gr = max(float((np.abs(OT.grft_cell(echo, grid, k, rows=r + grid.n_begin)) ** 2).max())
              for k in cells)
-    return {"ds_td": td, "ds_fd": fdv, "grft": gr}
+    ykt = KT.coarse_rows(echo, grid, ktc, Np=Np)[:, r]
+    kt = float((np.abs(ykt.T @ KT.fine_matrix(grid)) ** 2).max())
+    return {"ds_td": td, "ds_fd": fdv, "ds_kt": kt, "grft": gr}
 
 
 @pytest.mark.parametrize("snr,seed", [(-16.0, 1), (-15.0, 2), (-14.0, 3), (-13.0, 4)])
@@ -43,17 +46,23 @@ def test_trial_statistics_and_decisions_match_oracle(snr, seed):
     r = sc["radar"]
     plans = {"ds_td": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"]),
              "ds_fd": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"],
-                           mgift="fd")}
+                           mgift="fd"),
+             "ds_kt": Plan(r.fc, r.fs, r.prf, sc["M"], sc["N"], sc["order"], sc["axes"],
+                           mgift="kt")}
     grid = make_grid(Radar(r.fc, r.fs, r.prf), sc["M"], sc["N"], sc["order"],
                      [Axis(*a) for a in sc["axes"]])
     gamma2 = plans["ds_td"].threshold(1.0, PD_PFA)
     rng = np.random.Generator(np.random.PCG64(seed))
     tg = synth.draw_targets(rng, r, sc["M"], sc["N"], 1, snr, 1.0, sc["v"], sc["a"], sc["j"])[0]
     echo = synth.make_echo(r, sc["M"], sc["N"], [tg], 1.0, rng)
-    res, cells, rows, kt = pd_trial(plans, torch.from_numpy(echo).cuda(), tg, gamma2)
+    res, cells, rows, kt, ktc = pd_trial(plans, torch.from_numpy(echo).cuda(), tg, gamma2)
     assert kt in cells
-    ref = _oracle_stats(echo.astype(np.complex128), grid, cells, rows)
-    for d, tol in (("ds_td", 1e-3), ("ds_fd", 1e-3), ("grft", 1e-5)):
+    q, i2c = KT.coarse_params(grid, KT.lattice(grid), ktc)
+    i1 = int(np.floor(tg.v / grid.steps[0] + 0.5))
+    assert q * sc["M"] - sc["M"] // 2 <= i1 < q * sc["M"] + sc["M"] // 2
+    assert abs(tg.a / grid.steps[1] - i2c) <= grid.R / 2 + 0.5
+    ref = _oracle_stats(echo.astype(np.complex128), grid, cells, rows, ktc)
+    for d, tol in (("ds_td", 1e-3), ("ds_fd", 1e-3), ("ds_kt", 1e-5), ("grft", 1e-5)):
         stat, hit = res[d]
         assert abs(stat - ref[d]) <= tol * ref[d], (d, stat, ref[d])
         if abs(ref[d] - gamma2) > tol * ref[d]:
@@ -65,5 +74,6 @@ def test_pd_bench_mode_runs():
                           "--trials", "3"], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr[-2000:]
     d = json.loads(out.stdout.strip().splitlines()[-1])
-    assert set(d["pd"]) == {"ds_td", "ds_fd", "grft"} and len(d["snr_db"]) == len(d["pd"]["ds_td"])
+    assert set(d["pd"]) == {"ds_td", "ds_fd", "ds_kt", "grft"}
+    assert len(d["snr_db"]) == len(d["pd"]["ds_td"])
     assert d["value"] > 0
