@@ -205,7 +205,9 @@ def main():
               "peak": HBM_GBPS, "unit": "GB/s",
               "frac": round(gather_bytes / gather_avg_s / 1e9 / HBM_GBPS, 4),
               "avg_launch_ms": round(gather_avg_s * 1e3, 4),
-              "bytes_per_launch": gather_bytes}
+              "bytes_per_launch": gather_bytes,
+              "note": "elapsed time on the producer stream while the fine search of the "
+                      "previous batch runs beside it (two-stream pipeline)"}
     log(f"fine kernel: {achieved:.1f} TFLOP/s ({achieved / peak:.1%} of {peak}); "
         f"gather {gather['achieved']:.0f} GB/s")
 

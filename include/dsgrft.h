@@ -20,8 +20,12 @@
  *  - "d_" arguments are device pointers on the current HIP device; "h_"
  *    arguments are host pointers.  The caller owns every I/O buffer.
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
- *    device work is enqueued on it; no entry point synchronises the stream
- *    unless its comment says so.  A plan may be used by one stream at a time.
+ *    device work is ordered on it; no entry point synchronises the stream
+ *    unless its comment says so.  dsgrft_search and dsgrft_search_full also
+ *    run part of their work on a second stream owned by the plan; that work
+ *    starts after everything enqueued on `stream` before the call and
+ *    finishes before anything enqueued on `stream` after it.  A plan may be
+ *    used by one stream at a time.
  *  - The plan owns its device workspace, allocated in dsgrft_plan_create.
  *    Execution entry points allocate nothing.
  *  - Errors are reported as status codes only; nothing aborts or prints.

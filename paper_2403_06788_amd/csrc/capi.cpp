@@ -44,10 +44,14 @@ hipError_t dalloc(T **p, size_t bytes, size_t &total) {
 void release(dsgrft_plan p) {
   if (!p) return;
   void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->u_off, p->u_psi,
-                  p->G, p->g_scale, p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
+                  p->Gbuf[0], p->gscbuf[0], p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
                   p->kt_spec, p->kt_invd, p->packed, p->det_ws, p->adj_ws};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
+  hipEvent_t evs[] = {p->ev_start, p->ev_g[0], p->ev_g[1], p->ev_f[0], p->ev_f[1]};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   delete p;
 }
 
@@ -85,41 +89,62 @@ double gather_bytes(dsgrft_form form, int split) {
 
 // Stages a0..a4 over n listed cells, batch by batch.  pmax/argf may be NULL
 // (full-map only), full may be NULL.
+//
+// Two-stream pipeline: the producer stream `aux` runs the per-echo transforms
+// and, per batch of gathered units, the unit tables, the coarse compensation
+// and the gather into slot b % 2 of the gathered buffer; the caller's stream
+// runs the fine search of batch b on that slot and the reductions.  Events
+// order the slots (the fine search of b waits for its gather; the gather of
+// b + 2 waits until the fine search of b has read the slot), so the
+// memory-bound producer work of batch b + 1 overlaps the compute-bound fine
+// search of batch b.  `aux` first waits for everything already enqueued on
+// the caller's stream, and the caller's stream waits for every gather, so
+// the call stays ordered on the caller's stream as a whole.
 dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
                          const float2 *echo, const int64_t *cells,
                          int64_t cc_begin, int64_t n, float *pmax, int32_t *argf,
                          float *full, hipStream_t s) {
   const int64_t Bc = p->batch_cells, Bu = p->batch_units;
-  if (p->fd) DS_TRY(launch_range_fft(p, echo, s));
-  if (p->kt) DS_TRY(launch_keystone(p, s));
+  hipStream_t sa = p->aux;
+  DS_TRY(hipEventRecord(p->ev_start, s));
+  DS_TRY(hipStreamWaitEvent(sa, p->ev_start, 0));
+  if (p->fd) DS_TRY(launch_range_fft(p, echo, sa));
+  if (p->kt) DS_TRY(launch_keystone(p, sa));
   const GatherSrc src = gather_src(p, echo);
+  int64_t b = 0;
   for (int64_t c0 = 0; c0 < n; c0 += Bc) {
     const int64_t nc = (n - c0) < Bc ? (n - c0) : Bc;
     DS_TRY(launch_fill_u64(p->packed, nc * p->rows, s));
     const int64_t nut = nc * p->R3;
     const int64_t *cl = cells ? cells + c0 : nullptr;
     float *fl = full ? full + c0 * p->rows * p->n_fine : nullptr;
-    for (int64_t u0 = 0; u0 < nut; u0 += Bu) {
+    for (int64_t u0 = 0; u0 < nut; u0 += Bu, ++b) {
       const int64_t nu = (nut - u0) < Bu ? (nut - u0) : Bu;
-      DS_TRY(launch_unit_tables(p, cl, cc_begin + c0, u0, nu, s));
+      const int slot = (int)(b & 1);
+      p->G = p->Gbuf[slot];
+      p->g_scale = p->gscbuf[slot];
+      if (b >= 2) DS_TRY(hipStreamWaitEvent(sa, p->ev_f[slot], 0));
+      DS_TRY(launch_unit_tables(p, cl, cc_begin + c0, u0, nu, sa));
       if (p->kt)
-        DS_TRY(launch_kt_shift(p, cl, cc_begin + c0, u0, nu, s));
+        DS_TRY(launch_kt_shift(p, cl, cc_begin + c0, u0, nu, sa));
       else if (p->fd)
-        DS_TRY(launch_fd_shift(p, cl, cc_begin + c0, u0, nu, p->R3, s));
+        DS_TRY(launch_fd_shift(p, cl, cc_begin + c0, u0, nu, p->R3, sa));
       auto &pr = p->prof;
       const bool tg = pr.ng < pr.cap, tf = pr.nf < pr.cap;
       const double samples = (double)nu * p->rows * p->M;
       const double bg = gather_bytes(form, split);
-      if (tg) DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng], s));
+      if (tg) DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng], sa));
       if (form == DSGRFT_FORM_F32 || form == DSGRFT_FORM_F32_FFT)
-        DS_TRY(launch_gather_f32(p, src, nu, s));
+        DS_TRY(launch_gather_f32(p, src, nu, sa));
       else
-        DS_TRY(launch_gather_lp(p, form, split, src, nu, s));
+        DS_TRY(launch_gather_lp(p, form, split, src, nu, sa));
       if (tg) {
-        DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng + 1], s));
+        DS_TRY(hipEventRecord(pr.ev_g[2 * pr.ng + 1], sa));
         pr.ng++;
         pr.gbytes += samples * (8.0 + bg);
       }
+      DS_TRY(hipEventRecord(p->ev_g[slot], sa));
+      DS_TRY(hipStreamWaitEvent(s, p->ev_g[slot], 0));
       if (tf) DS_TRY(hipEventRecord(pr.ev_f[2 * pr.nf], s));
       if (form == DSGRFT_FORM_F32)
         DS_TRY(launch_fine_f32(p, nu, u0, fl, 0, s));
@@ -133,6 +158,7 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
         pr.fcp += samples * p->C;
         pr.fflops += 8.0 * samples * p->C;
       }
+      DS_TRY(hipEventRecord(p->ev_f[slot], s));
     }
     if (pmax && argf)
       DS_TRY(launch_unpack(p, nc, pmax + c0 * p->rows, argf + c0 * p->rows, s));
@@ -352,7 +378,7 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
       dalloc(&p->F16, f16b, tot) != hipSuccess ||
       dalloc(&p->FBF16, f16b, tot) != hipSuccess ||
       dalloc(&p->F8, f16b ? (size_t)4 * p->Cp * p->Mp : 0, tot) != hipSuccess ||
-      dalloc(&p->g_scale, (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
+      dalloc(&p->gscbuf[0], 2 * (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
       (fft_form_supported(M) &&
        dalloc(&p->fft_tw, fft_table_elems(M, p->R, P) * sizeof(float2), tot) != hipSuccess) ||
       (p->fd &&
@@ -364,7 +390,7 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
         dalloc(&p->kt_invd, (size_t)p->fd_np * sizeof(double), tot) != hipSuccess)) ||
       dalloc(&p->u_off, (size_t)bu * p->Mp * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->u_psi, (size_t)bu * p->Mp * sizeof(float2), tot) != hipSuccess ||
-      dalloc((char **)&p->G, (size_t)bu * per_unit, tot) != hipSuccess ||
+      dalloc((char **)&p->Gbuf[0], 2 * (size_t)bu * per_unit, tot) != hipSuccess ||
       dalloc(&p->packed, (size_t)p->batch_cells * p->rows * 8, tot) != hipSuccess ||
       dalloc((char **)&p->det_ws, p->det_ws_bytes, tot) != hipSuccess ||
       dalloc(&p->adj_ws, p->adj_ws_bytes, tot) != hipSuccess) {
@@ -373,6 +399,20 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
     return DSGRFT_E_NOMEM;
   }
   p->ws_bytes = tot;
+  p->Gbuf[1] = (char *)p->Gbuf[0] + (size_t)bu * per_unit;
+  p->gscbuf[1] = p->gscbuf[0] + (size_t)bu * p->rows_p;
+  p->G = p->Gbuf[0];
+  p->g_scale = p->gscbuf[0];
+  if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_start, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_g[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_g[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_f[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_f[1], hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    release(p);
+    return DSGRFT_E_DEVICE;
+  }
   if (p->fft_tw) p->fft_chirp = p->fft_tw + M;
   if ((!p->kt && launch_fine_tables(p, nullptr) != hipSuccess) ||
       (p->fft_tw && launch_fft_tables(p, nullptr) != hipSuccess) ||

@@ -77,8 +77,14 @@ struct dsgrft_plan_s {
   uint4 *F8;            // e4m3 fragments (K blocks of 64), same 4 planes
   int32_t *u_off;       // [batch_units][Mp] unit range offsets
   float2 *u_psi;        // [batch_units][Mp] unit de-ramp phasors
-  void *G;              // gathered batch, max 8 bytes per (unit,row,pulse)
-  int32_t *g_scale;     // [batch_units][rows_p] per-row E8M0 codes (8-bit form)
+  void *G;              // gathered batch being produced or consumed (a slot
+                        //   of Gbuf), max 8 bytes per (unit,row,pulse)
+  int32_t *g_scale;     // [batch_units][rows_p] per-row E8M0 codes of that slot
+  void *Gbuf[2];        // two slots: batch b + 1 is gathered while the fine
+  int32_t *gscbuf[2];   //   search reads batch b
+  hipStream_t aux;      // producer stream of the search pipeline (tables,
+                        //   coarse compensation, gathers); default priority
+  hipEvent_t ev_start, ev_g[2], ev_f[2];  // ordering events of the pipeline
   float2 *fft_tw;       // [M] exp(+j 2 pi k / M) (FFT form; null if unsupported)
   float2 *fft_chirp;    // [R or 1][M] fine-acceleration chirps (FFT form)
   // frequency-domain mGIFT (cfg.mgift == 1)
