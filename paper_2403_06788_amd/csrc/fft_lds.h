@@ -5,7 +5,10 @@
 // all its groups before the barrier and writes after it, so the pass works in
 // place.  The radices are 16 with the remainder folded into the first pass (32
 // or 64) or a last pass of 4 or 8, so NP = 8192 takes three passes.  Twiddles
-// come from two small LDS tables, W^i = TH[i >> 7] TL[i & 127].
+// come from two small LDS tables, W^i = TH[i >> 7] TL[i & 127].  Element i
+// sits at LDS index i + i / 32 (one pad entry per 32): the span-1 pass writes
+// with a stride of R entries, which would otherwise put every lane of a
+// wavefront in the same bank; contiguous accesses stay contiguous.
 #pragma once
 
 #include "fft_reg.h"
@@ -16,6 +19,12 @@ using fftreg::cmulf;
 using fftreg::fft_reg;
 
 __device__ inline float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+// Padded LDS position of element i, and the LDS entries an NP-point transform
+// occupies.
+__device__ inline int pidx(int i) { return i + (i >> 5); }
+template <int NP>
+constexpr int lds_len() { return NP + NP / 32; }
 
 // Twiddle W^i = exp(+j 2 pi i / NP) from the two LDS tables.
 struct TwLds {
@@ -38,7 +47,7 @@ __device__ inline void stockham_pass(float2 *X, const TwLds &tw) {
       const int k = j % NS;
 #pragma unroll
       for (int t = 0; t < R; ++t) {
-        float2 x = X[j + t * NG];
+        float2 x = X[pidx(j + t * NG)];
         if (NS > 1 && t > 0) {
           const float2 w = tw(t * k * (NP / (NS * R)));
           x = cmulf(x, INV ? w : conjf2(w));
@@ -60,7 +69,7 @@ __device__ inline void stockham_pass(float2 *X, const TwLds &tw) {
       fft_reg<R>(v[g]);
       const int d = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int t = 0; t < R; ++t) X[d + t * NS] = INV ? v[g][t] : conjf2(v[g][t]);
+      for (int t = 0; t < R; ++t) X[pidx(d + t * NS)] = INV ? v[g][t] : conjf2(v[g][t]);
     }
   }
   __syncthreads();

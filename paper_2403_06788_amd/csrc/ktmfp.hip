@@ -37,6 +37,8 @@ using fftreg::cmulf;
 using fftlds::TwLds;
 using fftlds::fft_lds;
 using fftlds::load_twiddles;
+using fftlds::lds_len;
+using fftlds::pidx;
 
 constexpr int KS_LDS = 8192;  // complex64 entries of the keystone's LDS tile
 
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(256) void k_kt_shift(
     const double *__restrict__ invd, const int64_t *cells, int64_t cc_base,
     int64_t unit0, int M, int R, int q_lo, int n_a, int ilo1, int rows, int rows_p,
     int n_begin, float2 *__restrict__ E) {
-  __shared__ float2 X[NP];
+  __shared__ float2 X[lds_len<NP>()];
   __shared__ float2 t_lo[128], t_hi[NP / 128 > 1 ? NP / 128 : 1];
   const TwLds tl = load_twiddles<NP>(tw, t_lo, t_hi);
   const int tid = threadIdx.x;
@@ -141,22 +143,38 @@ __global__ __launch_bounds__(256) void k_kt_shift(
   const int64_t xi2 = floor_div(num2, RM2);
   const double xf2 = (double)(num2 - xi2 * RM2) / (double)RM2;
   const float2 *sp = kspec + (int64_t)m * NP;
-  for (int kk = tid; kk < NP; kk += 256) {
-    const int ks = kk < NP / 2 ? kk : kk - NP;
-    const int ii = (int)(((int64_t)ks * xi2) & (NP - 1));   // (k_s xi2) mod NP
-    double turns = g * (double)ks * invd[kk] -
-                   ((double)ii + (double)ks * xf2) * (1.0 / (double)NP);
-    turns -= rint(turns);
-    float s, c;
-    sincospif(2.0f * (float)turns, &s, &c);
-    X[kk] = cmulf(sp[kk], make_float2(c, s));
+  // loads in groups of LB per thread, all issued before the first is used
+  constexpr int EPT = (NP + 255) / 256, LB = EPT < 16 ? EPT : 16;
+  for (int e0 = 0; e0 < EPT; e0 += LB) {
+    float2 sv[LB];
+    double iv[LB];
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int kk = tid + 256 * (e0 + e);
+      sv[e] = kk < NP ? sp[kk] : make_float2(0.f, 0.f);
+      iv[e] = kk < NP ? invd[kk] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int kk = tid + 256 * (e0 + e);
+      if (kk < NP) {
+        const int ks = kk < NP / 2 ? kk : kk - NP;
+        const int ii = (int)(((int64_t)ks * xi2) & (NP - 1));   // (k_s xi2) mod NP
+        double turns = g * (double)ks * iv[e] -
+                       ((double)ii + (double)ks * xf2) * (1.0 / (double)NP);
+        turns -= rint(turns);
+        float s, c;
+        sincospif(2.0f * (float)turns, &s, &c);
+        X[pidx(kk)] = cmulf(sv[e], make_float2(c, s));
+      }
+    }
   }
   __syncthreads();
   fft_lds<NP, 1, true>(X, tl);
   const float inv = 1.0f / (float)NP;
   float2 *o = E + ((int64_t)u * M + m) * rows_p;
   for (int r = tid; r < rows_p; r += 256) {
-    const float2 y = X[n_begin + r < NP ? n_begin + r : 0];
+    const float2 y = X[pidx(n_begin + r < NP ? n_begin + r : 0)];
     o[r] = (r < rows) ? make_float2(y.x * inv, y.y * inv) : make_float2(0.f, 0.f);
   }
 }

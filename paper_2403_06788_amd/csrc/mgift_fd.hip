@@ -29,20 +29,35 @@ using fftreg::cmulf;
 using fftlds::TwLds;
 using fftlds::fft_lds;
 using fftlds::load_twiddles;
+using fftlds::lds_len;
+using fftlds::pidx;
 
 template <int NP>
 __global__ __launch_bounds__(256) void k_range_fft(const float2 *__restrict__ echo,
                                                    int N, const float2 *__restrict__ tw,
                                                    float2 *__restrict__ spec) {
-  __shared__ float2 X[NP];
+  __shared__ float2 X[lds_len<NP>()];
   __shared__ float2 t_lo[128], t_hi[NP / 128 > 1 ? NP / 128 : 1];
   const TwLds tl = load_twiddles<NP>(tw, t_lo, t_hi);
   const int m = blockIdx.x;
-  for (int n = threadIdx.x; n < NP; n += 256)
-    X[n] = (n < N) ? echo[(int64_t)m * N + n] : make_float2(0.f, 0.f);
+  // loads in groups of LB per thread, all issued before the first is used
+  constexpr int EPT = (NP + 255) / 256, LB = EPT < 16 ? EPT : 16;
+  for (int e0 = 0; e0 < EPT; e0 += LB) {
+    float2 sv[LB];
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int n = threadIdx.x + 256 * (e0 + e);
+      sv[e] = (n < N && n < NP) ? echo[(int64_t)m * N + n] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int n = threadIdx.x + 256 * (e0 + e);
+      if (n < NP) X[pidx(n)] = sv[e];
+    }
+  }
   __syncthreads();
   fft_lds<NP, 1, false>(X, tl);
-  for (int k = threadIdx.x; k < NP; k += 256) spec[(int64_t)m * NP + k] = X[k];
+  for (int k = threadIdx.x; k < NP; k += 256) spec[(int64_t)m * NP + k] = X[pidx(k)];
 }
 
 template <int NP>
@@ -51,7 +66,7 @@ __global__ __launch_bounds__(256) void k_fd_shift(
     const int64_t *cells, int64_t cc_base, int64_t unit0, int M, int R3, int R,
     int P, int K0, int K1, int K2, int i0, int i1, int i2, Lat L, int rows,
     int rows_p, int n_begin, float2 *__restrict__ E) {
-  __shared__ float2 X[NP];
+  __shared__ float2 X[lds_len<NP>()];
   constexpr int A0 = (NP + 127) / 128;            // -min(a), k_s = 64 a + c
   constexpr int NA = NP / 64 > 2 ? NP / 64 : 2;
   __shared__ float2 TA[NA], TC[64];
@@ -80,19 +95,32 @@ __global__ __launch_bounds__(256) void k_fd_shift(
   }
   __syncthreads();
   const float2 *sp = spec + (int64_t)m * NP;
-  for (int kk = tid; kk < NP; kk += 256) {
-    const int ks = kk < NP / 2 ? kk : kk - NP;
-    const int ii = (int)(((int64_t)ks * xi) & (NP - 1));  // (k_s xi) mod NP
-    const int a = ks >> 6, c = ks & 63;                    // k_s = 64 a + c
-    const float2 w = cmulf(cmulf(tl(ii), TA[a + A0]), TC[c]);
-    X[kk] = cmulf(sp[kk], w);
+  constexpr int EPT = (NP + 255) / 256, LB = EPT < 16 ? EPT : 16;
+  for (int e0 = 0; e0 < EPT; e0 += LB) {
+    float2 sv[LB];
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int kk = tid + 256 * (e0 + e);
+      sv[e] = kk < NP ? sp[kk] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int e = 0; e < LB; ++e) {
+      const int kk = tid + 256 * (e0 + e);
+      if (kk < NP) {
+        const int ks = kk < NP / 2 ? kk : kk - NP;
+        const int ii = (int)(((int64_t)ks * xi) & (NP - 1));  // (k_s xi) mod NP
+        const int a = ks >> 6, c = ks & 63;                    // k_s = 64 a + c
+        const float2 w = cmulf(cmulf(tl(ii), TA[a + A0]), TC[c]);
+        X[pidx(kk)] = cmulf(sv[e], w);
+      }
+    }
   }
   __syncthreads();
   fft_lds<NP, 1, true>(X, tl);
   const float inv = 1.0f / (float)NP;
   float2 *out = E + ((int64_t)u * M + m) * rows_p;
   for (int r = tid; r < rows_p; r += 256) {
-    const float2 y = X[n_begin + r < NP ? n_begin + r : 0];
+    const float2 y = X[pidx(n_begin + r < NP ? n_begin + r : 0)];
     out[r] = (r < rows) ? make_float2(y.x * inv, y.y * inv) : make_float2(0.f, 0.f);
   }
 }
