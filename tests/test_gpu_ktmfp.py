@@ -228,3 +228,35 @@ def test_kt_rejects_what_it_does_not_support():
     th = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
     with pytest.raises(DsgrftError, match="unsupported"):
         p.adjoint_forward(e, th)
+
+
+def test_kt_config3_sampled_rows_golden(full3):
+    """The benchmark workload at full size (its plan and batching) against the
+    oracle's reduced map on 24 sampled rows of three coarse cells, stored in
+    tests/golden/kt_config3_rows.json by tests/golden/make_kt_config3.py (which
+    calls only the oracle): FP32 tolerance, fine index exact where the
+    oracle's top-two gap exceeds twice the tolerance."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "kt_config3_rows.json")
+    with open(path) as f:
+        d = json.load(f)
+    p = full3["plan"]
+    assert p.fd_pad == d["pad_length"] and p.n_coarse == d["n_coarse"]
+    echo = torch.from_numpy(synth.config_case(3)["echo"]).cuda()
+    cells = [int(k) for k in d["cells"]]
+    pm, af = p.search(echo, "f32fft", 1, cells=torch.tensor(cells, dtype=torch.int64))
+    pm, af = pm.cpu().numpy(), af.cpu().numpy()
+    rows = np.array(d["rows"])
+    scale = max(max(v["pmax"]) for v in d["cells"].values())
+    checked = 0
+    for i, k in enumerate(cells):
+        ref = d["cells"][str(k)]
+        err = np.abs(pm[i, rows] - np.array(ref["pmax"])).max() / scale
+        assert err <= TOL, (k, err)
+        for j, r in enumerate(rows):
+            if ref["pmax"][j] - ref["second"][j] > 2 * TOL * scale:
+                assert af[i, r] == ref["argf"][j], (k, r)
+                checked += 1
+    assert checked > 0
