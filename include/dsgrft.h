@@ -289,9 +289,10 @@ dsgrft_status dsgrft_refine(dsgrft_plan plan, const void *d_echo,
                             double *d_J, void *stream);
 
 /* Kernel timing for measurement.  Between dsgrft_profile_begin and
- * dsgrft_profile_end the plan records a HIP event pair (on the caller's
- * stream) around each launch of the gather kernel (stages a1 + a2) and of
- * the fine-search kernel (stages a3 + a4) issued by dsgrft_search, for at
+ * dsgrft_profile_end the plan records a HIP event pair around each launch of
+ * the gather kernel (stages a1 + a2, on the plan's producer stream, where it
+ * may run beside a fine search) and of the fine-search kernel (stages a3 +
+ * a4, on the caller's stream) issued by dsgrft_search, for at
  * most `capacity` launches of each; later launches are not timed.  begin
  * creates the events (it is not an execution call) and resets the counters;
  * end synchronises the device, sums the event durations and destroys the

@@ -25,8 +25,9 @@
 // blocks of 32 x 32 MFMAs (fine cells on the MFMA rows, range rows on its
 // columns).  The wider wave tile reuses each fragment read from LDS for more
 // MFMAs: the kernel is bound by LDS traffic (copies in plus fragment reads),
-// not by the MFMA issue.  Accumulators live in AGPRs.  Operand fragments are
-// stored pre-swizzled in global memory.
+// not by the MFMA issue.  Accumulators live in the unified register file
+// (the fp16 split-1 kernel: 222 registers, two waves per SIMD).  Operand
+// fragments are stored pre-swizzled in global memory.
 //
 // Pipeline (one K step):
 //  * operands move global -> LDS with direct LDS-DMA loads (16 bytes per
