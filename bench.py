@@ -48,6 +48,19 @@ def recorded_traffic(form, split):
     return d.get("bytes_per_launch")
 
 
+def recorded_mfma_util(form, split):
+    """Executed-MFMA utilisation of the fine kernel (MFMA-busy cycles over
+    active cycles x SIMDs) from the committed rocprofv3 counter summary, or
+    None if absent or taken on another kernel version."""
+    try:
+        d = json.load(open(os.path.join(ROOT, "profiles", f"fine_mfma_{form}_m1024_mfma_util.json")))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha") != kernel_hash() or d.get("form") != f"{form}x{split}":
+        return None
+    return round(d.get("mfma_util"), 4)
+
+
 def oracle_rows(echo, grid, cells, rows, mgift="td"):
     """Oracle power rows for sampled (cell, rows): {cell: P [rows, n_fine]}."""
     import numpy as np
@@ -196,6 +209,7 @@ def main():
     roofline = {"bound": "alu" if fft else "mfma", "achieved": round(achieved, 2),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": None if fft else recorded_traffic(args.form, args.split),
+                "mfma_util": None if fft else recorded_mfma_util(args.form, args.split),
                 "kernel": f"k_fine_fft_w<{plan.M // 64}>" if fft
                           else f"k_fine_mfma<{args.form}, split {args.split}>",
                 "avg_launch_ms": round(fine_avg_s * 1e3, 4),
