@@ -40,7 +40,7 @@ def test_status_strings():
 
 
 def _create(fc=1e9, fs=1e7, prf=500.0, M=64, N=256, order=1, axes=((-150, 150),),
-            kappa=1.0, rows=(0, 0), batch=0, c=3e8):
+            kappa=1.0, rows=(0, 0), batch=0, c=3e8, mgift=0):
     L = _lib.lib()
     r = _lib.Radar(fc, fs, prf, c, kappa)
     cfg = _lib.Config()
@@ -49,6 +49,7 @@ def _create(fc=1e9, fs=1e7, prf=500.0, M=64, N=256, order=1, axes=((-150, 150),)
     for p, ax in enumerate(axes):
         cfg.axis[p].min, cfg.axis[p].max = ax
     cfg.batch = batch
+    cfg.mgift = mgift
     h = C.c_void_p()
     return L.dsgrft_plan_create(C.byref(r), C.byref(cfg), C.byref(h))
 
@@ -61,6 +62,7 @@ def _create(fc=1e9, fs=1e7, prf=500.0, M=64, N=256, order=1, axes=((-150, 150),)
     dict(rows=(10, 5)), dict(rows=(0, 300)), dict(rows=(-1, 10)),
     dict(batch=-1),
     dict(M=2048, order=3, axes=((-1e12, 1e12), (-1, 1), (-1, 1))),  # numerator overflow
+    dict(mgift=3), dict(mgift=-1),      # no such coarse stage
 ])
 def test_plan_create_rejects_invalid(kw):
     assert _create(**kw) == 1
@@ -68,6 +70,55 @@ def test_plan_create_rejects_invalid(kw):
 
 def test_plan_create_kappa_unsupported():
     assert _create(kappa=0.995) == 4
+
+
+@pytest.mark.parametrize("kw", [
+    dict(order=1),                                                 # DS-KT-MFP needs P = 2
+    dict(order=2, M=96, axes=((-150, 150), (-200, 200))),          # M not a power of two
+    dict(order=2, M=4096, axes=((-150, 150), (-200, 200))),        # M above 2048
+])
+def test_ktmfp_plan_limits(kw):
+    assert _create(mgift=2, **kw) == 4
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of dsgrft_radar, dsgrft_config, dsgrft_plan_info and
+    dsgrft_peak have the C header's sizes and field offsets (a host C program
+    built with gcc prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    mirrors = {"dsgrft_radar": _lib.Radar, "dsgrft_config": _lib.Config,
+               "dsgrft_plan_info": _lib.PlanInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dsgrft.h"',
+             "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines.append('  printf("dsgrft_peak size %zu\\n", sizeof(dsgrft_peak));')
+    for fname in _lib.PEAK_DTYPE.names:
+        cf = "pad_" if fname == "pad" else fname
+        lines.append(f'  printf("dsgrft_peak {fname} %zu\\n", offsetof(dsgrft_peak, {cf}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        s, f, v = ln.split()
+        got[(s, f)] = int(v)
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+    assert got[("dsgrft_peak", "size")] == _lib.PEAK_DTYPE.itemsize
+    for fname in _lib.PEAK_DTYPE.names:
+        assert got[("dsgrft_peak", fname)] == _lib.PEAK_DTYPE.fields[fname][1], fname
 
 
 def test_null_pointers_rejected():
