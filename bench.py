@@ -127,9 +127,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the search "
-                          "shards over coarse cells but multi-GPU runs are "
-                          "not part of it", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py measures one GPU; the search would shard "
+                          "over coarse cells across GPUs, but runs on several GPUs "
+                          "are not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

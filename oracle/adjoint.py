@@ -3,8 +3,8 @@
 Test infrastructure only: nothing in the product path imports this module.
 
 The paper defines the transforms only on the search lattice.  The off-grid
-objective used for peak refinement is this build's reading (documented with
-the other readings): for theta = (r0, v, a),
+objective used for peak refinement is a reading of its own, not the paper's:
+for theta = (r0, v, a),
 
   coarse cell   k_p = clamp(floor((theta_p / d_p - i_lo,p + 1/2) / R)),
                 i_c = its centre (Sec. IV-B lattice), p = v, a
