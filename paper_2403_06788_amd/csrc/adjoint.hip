@@ -11,17 +11,21 @@
 // Kronecker delta).  sinc(x - n) is evaluated as (-1)^(floor(x) - n)
 // sinpi(frac(x)) / (pi (x - n)), with a series near zero.
 //
-// Forward: a workgroup of 256 threads takes CB candidates; per chunk of 64
-// pulses the per-(candidate, pulse) quantities are formed once into LDS; each
-// group of 64 threads then takes every fourth pulse and sweeps its range taps
-// for all CB candidates, reusing every echo load CB times.  Accumulated per thread: Y, dY/dr0 (with
-// sinc'), sum s~ e t and sum s~ e t^2 (for dY/dv, dY/da), reduced at the end.
+// Forward: a workgroup of 256 threads takes CB candidates (2 for the forward
+// and gradient pass; 1 for refinement, whose batches are small: few
+// candidates per workgroup keep the registers low enough for several waves
+// per SIMD and, for a small batch, give enough workgroups); per chunk of
+// 256 / CB pulses the per-(candidate, pulse) quantities are formed once into
+// LDS; each group of 64 threads then takes every fourth pulse and sweeps its
+// range taps for all CB candidates, reusing every echo load CB times.
+// Accumulated per thread: Y, dY/dr0 (with sinc'), sum s~ e t and
+// sum s~ e t^2 (for dY/dv, dY/da), reduced at the end.
 #include "internal.h"
 
 namespace {
 
-constexpr int CB = 4;     // candidates per workgroup
-constexpr int MCH = 64;   // pulses per table chunk
+constexpr int CB_FWD = 2;  // candidates per workgroup, forward and gradients
+constexpr int CB_REF = 1;  // candidates per workgroup, refinement
 constexpr int TPB = 256;
 
 struct AdjCtx {
@@ -100,9 +104,11 @@ __device__ inline double block_sum(double v, double *red) {
 // Computes, for the candidates s_th[0..nb) (in LDS), the 8 complex sums (Y,
 // dY/dr0, sum s~ e t, sum s~ e t^2) into out[CB][8] (all threads receive
 // them).
+template <int CB>
 __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
                            const double (*s_th)[3], int nb, double (*out)[8],
                            Tap *s_tap, double *red) {
+  constexpr int MCH = TPB / CB;  // pulses per table chunk
   double acc[CB][8];
 #pragma unroll
   for (int b = 0; b < CB; ++b)
@@ -206,6 +212,7 @@ __device__ inline void finish(const AdjCtx &c, const double *o, double *sv) {
   sv[7] = ka * o[6];
 }
 
+template <int CB>
 __global__ __launch_bounds__(TPB) void k_adj_fwd(AdjCtx c, const float2 *__restrict__ echo,
                                                  const double *__restrict__ theta, int B,
                                                  double *__restrict__ J,
@@ -220,7 +227,7 @@ __global__ __launch_bounds__(TPB) void k_adj_fwd(AdjCtx c, const float2 *__restr
     s_th[b][q] = (b < nb) ? theta[(b0 + b) * 3 + q] : 0.0;
   }
   double out[CB][8];
-  eval_block(c, echo, s_th, nb, out, s_tap, red);
+  eval_block<CB>(c, echo, s_th, nb, out, s_tap, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
@@ -318,6 +325,7 @@ __global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__rest
 // kept if J does not decrease (radius doubled, at most 2), otherwise the
 // radius is halved.  The fine indices stay inside the starting coarse cell,
 // r0 inside [0, N-1] bins.
+template <int CB>
 __global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restrict__ echo,
                                                 double *__restrict__ theta, int B, int iters,
                                                 double *__restrict__ Jout) {
@@ -365,7 +373,7 @@ __global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restri
   };
   double out[CB][8], sv[CB][8];
   publish(th);
-  eval_block(c, echo, s_th, nb, out, s_tap, red);
+  eval_block<CB>(c, echo, s_th, nb, out, s_tap, red);
 #pragma unroll
   for (int b = 0; b < CB; ++b) {
     finish(c, out[b], sv[b]);
@@ -391,7 +399,7 @@ __global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restri
     }
     double po[CB][8];
     publish(prop);
-    eval_block(c, echo, s_th, nb, po, s_tap, red);
+    eval_block<CB>(c, echo, s_th, nb, po, s_tap, red);
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
       double ps[8];
@@ -445,7 +453,8 @@ AdjCtx make_ctx(dsgrft_plan p) {
 hipError_t launch_adjoint_forward(dsgrft_plan p, const float2 *echo,
                                   const double *theta, int B, double *J,
                                   double *saved, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_fwd, dim3((B + CB - 1) / CB), dim3(TPB), 0, s, make_ctx(p),
+  hipLaunchKernelGGL(k_adj_fwd<CB_FWD>, dim3((B + CB_FWD - 1) / CB_FWD), dim3(TPB), 0, s,
+                     make_ctx(p),
                      echo, theta, B, J, saved);
   return hipGetLastError();
 }
@@ -469,7 +478,8 @@ hipError_t launch_adjoint_backward(dsgrft_plan p, const float2 *echo,
 
 hipError_t launch_refine(dsgrft_plan p, const float2 *echo, double *theta, int B,
                          int iters, double *J, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine, dim3((B + CB - 1) / CB), dim3(TPB), 0, s, make_ctx(p),
+  hipLaunchKernelGGL(k_refine<CB_REF>, dim3((B + CB_REF - 1) / CB_REF), dim3(TPB), 0, s,
+                     make_ctx(p),
                      echo, theta, B, iters, J);
   return hipGetLastError();
 }

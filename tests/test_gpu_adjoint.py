@@ -92,7 +92,7 @@ def test_autograd_function_and_central_differences(p2):
         for q in range(3):
             e = np.zeros(3)
             e[q] = hs[q]
-            tp = torch.tensor([th0[b] + e, th0[b] - e], dtype=torch.float64)
+            tp = torch.from_numpy(np.stack([th0[b] + e, th0[b] - e])).to(torch.float64)
             Jp, _ = plan.adjoint_forward(p2["echo_dev"], tp)
             Jp = Jp.cpu().numpy()
             fd = (Jp[0] - Jp[1]) / (2 * hs[q])
