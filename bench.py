@@ -333,6 +333,9 @@ def _sync():
     torch.cuda.synchronize()
 
 
+ADJ_FLOPS_PER_TAP = 20
+
+
 def bench_adjoint(args):
     """M=512 adjoint: forward + backward over 4096 candidates, gradient checks
     and off-grid refinement of the target candidates."""
@@ -362,6 +365,25 @@ def bench_adjoint(args):
         gt, ge = step()
     _sync()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # dominant kernel: the forward (k_adj_fwd), timed alone with events on the
+    # stream it is launched on (torch's current stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nrep = 5
+    ev0.record()
+    for _ in range(nrep):
+        plan.adjoint_forward(echo, theta)
+    ev1.record()
+    _sync()
+    fwd_s = ev0.elapsed_time(ev1) * 1e-3 / nrep
+    # FP64 work per (candidate, pulse, range tap): distance (1), reciprocal
+    # (two Newton steps on a single-precision seed, 8), weight and derivative
+    # (3), four accumulations (8)
+    fwd_flops = float(len(th)) * plan.M * c["N"] * ADJ_FLOPS_PER_TAP
+    roofline = {"bound": "alu", "achieved": round(fwd_flops / fwd_s / 1e12, 2),
+                "peak": 78.6, "unit": "TFLOP/s",
+                "frac": round(fwd_flops / fwd_s / 1e12 / 78.6, 4), "traffic": None,
+                "kernel": "k_adj_fwd (FP64)", "avg_launch_ms": round(fwd_s * 1e3, 4),
+                "flops_per_launch": fwd_flops}
     # device central differences, candidates away from coarse-cell edges
     J, _ = plan.adjoint_forward(echo, theta)
     gt = gt.cpu().numpy()
@@ -410,6 +432,7 @@ def bench_adjoint(args):
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": "adjoint, M=512 pulses, N=2048 bins, P=2, 16 targets at "
                                   "-10 dB, 4096 candidates (16 jittered per target + 3840 uniform)"},
+           "roofline": roofline,
            "grad_vs_central_diff_max_rel": fd_err, "grad_vs_oracle_max_rel": o_err,
            "fd_candidates": int(len(idx)),
            "refine": {"candidates": 16 * len(case["targets"]), "iters": 40,
