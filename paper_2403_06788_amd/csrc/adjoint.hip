@@ -149,28 +149,55 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
         Bc[b] = sg * T.cp;
         d0[b] = (double)(T.xi - lane) + T.xf;
       }
+      // taps in pairs (n, n + 64) with separate accumulators, so that the
+      // two FMA chains per sum advance independently; summed after the sweep
+      double sr2[CB], si2[CB], dr2[CB], di2[CB];
+#pragma unroll
+      for (int b = 0; b < CB; ++b) sr2[b] = si2[b] = dr2[b] = di2[b] = 0.0;
       int j = 0;
-      for (int n = lane; n < c.N; n += 64, ++j) {
-        const float2 s = row[n];
-        const double sx = (double)s.x, sy = (double)s.y;
+      for (int n = lane; n < c.N; n += 128, j += 2) {
+        const float2 s0 = row[n];
+        const bool two = n + 64 < c.N;
+        const float2 s1 = two ? row[n + 64] : make_float2(0.f, 0.f);
+        const double sx0 = (double)s0.x, sy0 = (double)s0.y;
+        const double sx1 = (double)s1.x, sy1 = (double)s1.y;
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
           if (b < nb) {
-            const double d = d0[b] - (double)(64 * j);
-            double w, dw;
-            if (fabs(d) < 1e-4) {
-              sinc_series(d, w, dw);
+            const double da = d0[b] - (double)(64 * j);
+            const double db = da - 64.0;
+            double wa, dwa, wb, dwb;
+            if (fabs(da) < 1e-4) {
+              sinc_series(da, wa, dwa);
             } else {
-              const double r = recip(d);
-              w = A[b] * r;
-              dw = (Bc[b] - w) * r;
+              const double r = recip(da);
+              wa = A[b] * r;
+              dwa = (Bc[b] - wa) * r;
             }
-            sr[b] = fma(sx, w, sr[b]);
-            si[b] = fma(sy, w, si[b]);
-            dr_[b] = fma(sx, dw, dr_[b]);
-            di[b] = fma(sy, dw, di[b]);
+            if (fabs(db) < 1e-4) {
+              sinc_series(db, wb, dwb);
+            } else {
+              const double r = recip(db);
+              wb = A[b] * r;
+              dwb = (Bc[b] - wb) * r;
+            }
+            sr[b] = fma(sx0, wa, sr[b]);
+            si[b] = fma(sy0, wa, si[b]);
+            dr_[b] = fma(sx0, dwa, dr_[b]);
+            di[b] = fma(sy0, dwa, di[b]);
+            sr2[b] = fma(sx1, wb, sr2[b]);
+            si2[b] = fma(sy1, wb, si2[b]);
+            dr2[b] = fma(sx1, dwb, dr2[b]);
+            di2[b] = fma(sy1, dwb, di2[b]);
           }
         }
+      }
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        sr[b] += sr2[b];
+        si[b] += si2[b];
+        dr_[b] += dr2[b];
+        di[b] += di2[b];
       }
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
