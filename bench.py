@@ -23,7 +23,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DS-GRFT cells·pulses/s (M=1024); MFMA vs FP32 speedup at rel err≤1e-3"
-PEAK_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3, "f32fft": 157.3}
+PEAK_TFLOPS = {"f16": 2500.0, "f16_3m": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3,
+               "f32fft": 157.3}
+DTYPE = {"f16_3m": "f16", "f32fft": "f32"}
+KERNEL = {"f16_3m": "k_fine_mfma3 (f16, three real products per complex product)"}
+FORM_TEXT = {"f16_3m": "f16 MFMA, three real products per complex product (Gauss), split 1, "
+                       "FP32 accumulation",
+             "f32fft": "FP32, fine velocities by slow-time FFT"}
 HBM_GBPS = 8000.0
 FINE_SRC = os.path.join(ROOT, "paper_2403_06788_amd", "csrc", "fine_mfma.hip")
 
@@ -107,7 +113,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", default="f16")
+    ap.add_argument("--form", default="f16_3m")
     ap.add_argument("--mgift", default="td", choices=("td", "fd"),
                     help="coarse compensation: time-domain gather or frequency domain")
     ap.add_argument("--split", type=int, default=1)
@@ -211,7 +217,7 @@ def main():
                 "traffic": None if fft else recorded_traffic(args.form, args.split),
                 "mfma_util": None if fft else recorded_mfma_util(args.form, args.split),
                 "kernel": f"k_fine_fft_w<{plan.M // 64}>" if fft
-                          else f"k_fine_mfma<{args.form}, split {args.split}>",
+                          else KERNEL.get(args.form, f"k_fine_mfma<{args.form}, split {args.split}>"),
                 "avg_launch_ms": round(fine_avg_s * 1e3, 4),
                 "flops_per_launch": fine_flops_launch,
                 "launches": prof["fine_launches"]}
@@ -243,7 +249,8 @@ def main():
                                          "argmax_checked": clear}
     # ---- other forms: one warm step each ----------------------------------
     if not args.no_sweep:
-        for form, split in (("f16", 2), ("f16", 3), ("f16", 4), ("bf16", 1), ("bf16", 2),
+        for form, split in (("f16_3m", 1), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4),
+                            ("bf16", 1), ("bf16", 2),
                             ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3),
                             ("fp8", 4), ("f32fft", 1)):
             if (form, split) == (args.form, args.split):
@@ -305,11 +312,12 @@ def main():
         "metric": METRIC, "value": value, "unit": "cells·pulses/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": args.form, "data": "synthetic",
+        "vs_baseline": None, "dtype": DTYPE.get(args.form, args.form), "data": "synthetic",
         "config": {"workload": "DS-GRFT search, M=1024 pulses, N=4096 range bins, "
                                "P=2 (v +-600 m/s, a +-50 m/s^2), 2460 coarse x 10^4 fine "
                                "cells, 8 targets at -20 dB, fc=1 GHz, fs=10 MHz, PRF=500 Hz",
-                   "form": f"{args.form} MFMA, split {args.split}, FP32 accumulation",
+                   "form": FORM_TEXT.get(args.form,
+                                         f"{args.form} MFMA, split {args.split}, FP32 accumulation"),
                    "mgift": "time-domain nearest-bin gather" if args.mgift == "td"
                             else "frequency-domain coarse compensation (Alg. 1)",
                    "cells": cells * plan.rows * plan.n_fine, "pulses": plan.M},
@@ -476,7 +484,7 @@ def bench_jerk(args):
     n = cells.numel()
     cp = float(n) * plan.rows * plan.n_fine * plan.M
     res = {}
-    for form, split in (("f16", 1), ("bf16", 1), ("bf16", 3)):
+    for form, split in (("f16_3m", 1), ("f16", 1), ("bf16", 1), ("bf16", 3)):
         plan.search(echo, form, split, cells=cells[:1])
         _sync()
         t0 = time.perf_counter()
@@ -495,7 +503,7 @@ def bench_jerk(args):
     res["f32x1"] = {"cells_pulses_per_s": 2 * plan.rows * plan.n_fine * plan.M / dt,
                     "sample_cells": 2, "s": round(dt, 3)}
     out = {"metric": "DS-GRFT cells·pulses/s (M=2048, P=3, 64-coarse-cell subset)",
-           "value": res["f16x1"]["cells_pulses_per_s"], "unit": "cells·pulses/s",
+           "value": res["f16_3mx1"]["cells_pulses_per_s"], "unit": "cells·pulses/s",
            "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
            "config": {"workload": "third-order search, M=2048 pulses, N=8192 bins, v +-900, "

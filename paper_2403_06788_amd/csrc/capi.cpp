@@ -62,14 +62,16 @@ bool on_plan_device(dsgrft_plan p) {
 
 dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
   if (p->kt && form != DSGRFT_FORM_F32_FFT)
-    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_F32_FFT) ? DSGRFT_E_UNSUPPORTED
-                                                                   : DSGRFT_E_INVALID;
+    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_F16_3M) ? DSGRFT_E_UNSUPPORTED
+                                                                  : DSGRFT_E_INVALID;
   switch (form) {
     case DSGRFT_FORM_F32:
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_F32_FFT:
       if (split != 1) return DSGRFT_E_INVALID;
       return p->fft_tw ? DSGRFT_OK : DSGRFT_E_UNSUPPORTED;
+    case DSGRFT_FORM_F16_3M:
+      return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_F16:
     case DSGRFT_FORM_BF16:
     case DSGRFT_FORM_FP8:

@@ -12,6 +12,9 @@
 // products taken are, by split count: 1: Fh Gh; 2: + Fl Gh; 3: + Fh Gl;
 // 4: + Fl Gl.
 //
+// k_fine_mfma3 (below) forms the fp16 split-1 product from three real
+// products per complex product instead of four.
+//
 // Operand formats: fp16 and bf16 (v_mfma_f32_32x32x16, 16 pulses per K
 // step, 1 KiB fragments) and OCP e4m3 (v_mfma_scale_f32_32x32x64_f8f6f4, 64
 // pulses per K step, 2 KiB fragments) whose E8M0 block scales carry the
@@ -429,6 +432,161 @@ __global__ __launch_bounds__(256, (Cfg<Op, SPLIT>::MINB)) void k_fine_mfma(
   }
 }
 
+// The fp16 search with three real products per complex product (Gauss's
+// form of the complex multiplication):
+//   P1 = Fr Gr,  P2 = Fi Gi,  P3 = (Fr + Fi)(Gr + Gi),
+//   Yr = P1 - P2,  Yi = P3 - P1 - P2,
+// 12 MFMAs per K step and wave instead of 16, same algorithmic result.  The
+// operand sums are formed in registers from the fp16 hi planes
+// (v_pk_add_f16, round to nearest even), so the tables and the gather are
+// those of the fp16 split-1 form; their rounding enters Yi only.  Under
+// sustained random-operand MFMA load the chip runs at a power-limited
+// clock, so a quarter fewer matrix products is a quarter less of the energy
+// that sets it.
+//
+// Tile and ring as k_fine_mfma<OpF16, 1>: 128 fine x 128 rows per
+// workgroup, 64 x 64 per wave (2 x 2 blocks of 32x32x16), four LDS stages
+// of 16 KiB filled by LDS-DMA three steps ahead.  The three accumulator sets
+// take 192 registers, so there is no second fragment set: each step reads
+// its own fragments after the barrier, and the other workgroup's wave on
+// the same SIMD (two per CU) issues its MFMAs meanwhile.
+__device__ inline uint4 add_h8(uint4 a, uint4 b) {
+  return __builtin_bit_cast(uint4, __builtin_bit_cast(h8, a) + __builtin_bit_cast(h8, b));
+}
+
+__global__ __launch_bounds__(256, 2) void k_fine_mfma3(
+    const uint4 *__restrict__ F, const uint4 *__restrict__ G,
+    unsigned long long *__restrict__ packed, float *__restrict__ full, int FB,
+    int NB, int KS, int64_t nunits, int64_t unit0, int R3, int C, int rows, int GN) {
+  constexpr int NST = 4, NBG = 4;
+  constexpr int CH = 16 * 64, CPT = CH / 256;  // 16 fragments per stage
+  __shared__ uint4 lds[NST][CH];
+
+  const int NT = NB / NBG, FT = FB >> 2;
+  const TileMap tm = map_tile(blockIdx.x, nunits * NT * FT, NT, FT, GN);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wf = wave & 1, wn = wave >> 1;
+  const int wbase = tid & ~63;
+
+  // Chunk c of a stage: lane c % 64, fragment c / 64: fine (re 0-3, im 4-7),
+  // then rows (re 8-11, im 12-15).
+  const uint4 *src[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int c = tid + 256 * j;
+    const int ln = c & 63, fi = c >> 6;
+    if (fi < 8) {
+      const int plane = fi >> 2, blk = fi & 3;
+      src[j] = F + (((int64_t)plane * FB + tm.ft * 4 + blk) * KS) * 64 + ln;
+    } else {
+      const int plane = (fi - 8) >> 2, blk = fi & 3;
+      src[j] = G + (((tm.u * 2 + plane) * NB + tm.nt * NBG + blk) * (int64_t)KS) * 64 + ln;
+    }
+  }
+  auto issue = [&](int stage) {
+    uint4 *dst = lds[stage % NST];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const unsigned la = __builtin_amdgcn_readfirstlane(
+          (unsigned)(size_t)(lds_void *)&dst[wbase + 256 * j]);
+      const uint4 *g = src[j] + (int64_t)stage * 64;
+      unsigned saved_m0;
+      asm volatile(
+          "s_mov_b32 %0, m0\n\t"
+          "s_mov_b32 m0, %1\n\t"
+          "s_nop 0\n\t"
+          "global_load_lds_dwordx4 %2, off\n\t"
+          "s_nop 0\n\t"
+          "s_mov_b32 m0, %0"
+          : "=&s"(saved_m0)
+          : "s"(la), "v"(g)
+          : "memory");
+    }
+  };
+
+  f16v acc[3][2][2];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[q][i][j] = f16v{};
+
+  const int nkt = KS;
+#pragma unroll
+  for (int s = 0; s < NST - 1; ++s)
+    if (s < nkt) issue(s);
+  for (int kt = 0; kt < nkt; ++kt) {
+    // copies issued: stages 0 .. min(kt + NST - 2, nkt - 1); stage kt needed
+    const int left = nkt - 1 - kt;
+    wait_copies_barrier<CPT>(left < NST - 2 ? left : NST - 2);
+    const uint4 *slot = lds[kt % NST];
+    uint4 fr[2], fi[2], gr[2], gi[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) fr[i] = slot[(wf * 2 + i) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) gr[j] = slot[(8 + wn * 2 + j) * 64 + lane];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) fi[i] = slot[(4 + wf * 2 + i) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) gi[j] = slot[(12 + wn * 2 + j) * 64 + lane];
+    // the slot of stage kt - 1: every wave has consumed it (its MFMAs of the
+    // previous step were issued before this barrier)
+    if (kt + NST - 1 < nkt) issue(kt + NST - 1);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[0][i][j] = OpF16::mma({{fr[i]}}, {{gr[j]}}, acc[0][i][j], 0, 0);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[1][i][j] = OpF16::mma({{fi[i]}}, {{gi[j]}}, acc[1][i][j], 0, 0);
+    uint4 fs[2], gs[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) fs[i] = add_h8(fr[i], fi[i]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) gs[j] = add_h8(gr[j], gi[j]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[2][i][j] = OpF16::mma({{fs[i]}}, {{gs[j]}}, acc[2][i][j], 0, 0);
+  }
+
+  // ---- epilogue as in k_fine_mfma ----------------------------------------
+  const int64_t ug = unit0 + tm.u;
+  const int64_t cpos = ug / R3;
+  const unsigned fbase = (unsigned)((ug % R3) * C);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
+    unsigned long long best = 0ull;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int fb0 = (tm.ft * 4 + wf * 2 + i) * 32 + 4 * (lane >> 5);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = fb0 + 8 * (r >> 2) + (r & 3);
+        const float p1 = acc[0][i][j][r], p2 = acc[1][i][j][r], p3 = acc[2][i][j][r];
+        const float yr = p1 - p2, yi = p3 - p1 - p2;
+        const float pw = yr * yr + yi * yi;
+        if (f < C) {
+          const unsigned ff = fbase + (unsigned)f;
+          const unsigned long long key =
+              ((unsigned long long)__float_as_uint(pw) << 32) | (0xffffffffu - ff);
+          best = umax64(best, key);
+          if (full != nullptr && n < rows)
+            full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pw;
+        }
+      }
+    }
+    best = umax64(best, shfl_xor64(best, 32));
+    if (lane < 32 && n < rows) atomicMax(&packed[cpos * rows + n], best);
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ull;
@@ -490,6 +648,14 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
   switch (form) {
     case DSGRFT_FORM_F16:
       return launch_split<OpF16>(p, p->F16, 0, split, nunits, unit0, full, s);
+    case DSGRFT_FORM_F16_3M: {
+      if (split != 1) return hipErrorInvalidValue;
+      const int64_t tiles = nunits * (p->NB / 4) * (p->FB / 4);
+      hipLaunchKernelGGL(k_fine_mfma3, dim3((unsigned)tiles), dim3(256), 0, s,
+                         (const uint4 *)p->F16, (const uint4 *)p->G, p->packed, full, p->FB,
+                         p->NB, p->Mp / OpF16::KSTEP, nunits, unit0, p->R3, p->C, p->rows, 8);
+      return hipGetLastError();
+    }
     case DSGRFT_FORM_BF16:
       return launch_split<OpBF16>(p, p->FBF16, 0, split, nunits, unit0, full, s);
     case DSGRFT_FORM_FP8:

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {("f32", 1): 1e-5, ("f16", 1): 1e-3, ("f16", 2): 1e-3, ("f16", 3): 1e-5,
        ("f16", 4): 1e-5, ("bf16", 1): 1e-2, ("bf16", 2): 1e-2, ("bf16", 3): 1e-4,
-       ("bf16", 4): 1e-4}
+       ("bf16", 4): 1e-4, ("f16_3m", 1): 1e-3}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -131,3 +131,9 @@ def test_repeat_runs_are_bitwise_identical(case):
     a = p.search(case["echo_dev"], "f16", 1)
     b = p.search(case["echo_dev"], "f16", 1)
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_three_product_form_takes_split_one_only(case):
+    from paper_2403_06788_amd._lib import DsgrftError
+    with pytest.raises(DsgrftError, match="invalid"):
+        case["plan"].search(case["echo_dev"], "f16_3m", 2)
