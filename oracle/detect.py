@@ -14,6 +14,12 @@ Test infrastructure only: nothing in the product path imports this module.
   (coarse cell major, then row); each carries its argmax fine cell.
 * Peak parameters (eq. (72), Alg. 3 with kappa = 1): r0 = n0 dr and
   (v, a, j) = (coarse centre + fine offset) * fine step, in float64.
+* Cell-averaging CFAR along range (not in the paper, whose detector is the
+  fixed LRT threshold): an entry (cell, row r) is a detection when its power
+  exceeds alpha times the mean of the training entries of the same cell,
+  rows r' with guard < |r' - r| <= guard + train inside the map.  The mean is
+  a float64 sum in increasing r' divided by the number of training entries;
+  an entry with no training entry is never a detection.
 """
 from __future__ import annotations
 
@@ -71,3 +77,30 @@ def peak_params(grid: Grid, k: int, n0: int, f: int):
     i = grid.lattice_point(k, f)
     v, a, j = grid.params(i)
     return n0 * grid.dr, v, a, j
+
+
+def ca_cfar(pmax: np.ndarray, guard: int, train: int, alpha: float) -> np.ndarray:
+    """Cell-averaging CFAR decisions on a reduced map [cells, rows] (float32
+    or float64 values): boolean mask of detections.  Rows are visited one at
+    a time; the training sum runs over r' in increasing order for all cells
+    at once, each step a float64 addition."""
+    p = np.asarray(pmax, dtype=np.float64)
+    n, rows = p.shape
+    hit = np.zeros((n, rows), dtype=bool)
+    for r in range(rows):
+        train_rows = [q for q in range(r - guard - train, r + guard + train + 1)
+                      if 0 <= q < rows and guard < abs(q - r)]
+        if not train_rows:
+            continue
+        acc = np.zeros(n)
+        for q in train_rows:
+            acc = acc + p[:, q]
+        mean = acc / float(len(train_rows))
+        hit[:, r] = p[:, r] > alpha * mean
+    return hit
+
+
+def cfar_alpha(n_train: int, pfa: float) -> float:
+    """CA-CFAR multiplier for exponentially distributed power with n_train
+    training entries: P_FA = (1 + alpha / n_train)^(-n_train)."""
+    return n_train * (pfa ** (-1.0 / n_train) - 1.0)
