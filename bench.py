@@ -198,6 +198,12 @@ def main():
     log(f"timed {args.steps} steps: {ms:.1f} ms/step, {value:.3e} cells*pulses/s")
     pm_main, af_main = pm.cpu().numpy(), af.cpu().numpy()
     peaks, count, best = plan.detect(pm, af, gamma2, cap=4096)
+    # cell-averaging CFAR along range on the same reduced map (beside the LRT)
+    plan.detect_cfar(pm, af, 2, 16, 1.5, cap=4096)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, cfar_count, _ = plan.detect_cfar(pm, af, 2, 16, 1.5, cap=4096)
+    cfar_ms = (time.perf_counter() - t) * 1e3
 
     fine_avg_s = prof["fine_ms"] / max(prof["fine_launches"], 1) * 1e-3
     fft = args.form == "f32fft"
@@ -327,6 +333,8 @@ def main():
         "speedup_vs_f32": round(value / f32_rate, 2),
         "rel_err": err,
         "detections": int(count),
+        "cfar": {"guard": 2, "train": 16, "alpha": 1.5, "detections": int(cfar_count),
+                 "ms": round(cfar_ms, 3)},
         "forms": forms,
         "forms_within_1e-3": sorted(ok_forms),
         "fastest_within_1e-3": None if fastest is None else {

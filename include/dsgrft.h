@@ -263,6 +263,23 @@ dsgrft_status dsgrft_detect(dsgrft_plan plan, const float *d_pmax,
                             int32_t *d_count, dsgrft_peak *d_best,
                             void *stream);
 
+/* Cell-averaging CFAR along range on a reduced map (a detector beside the
+ * paper's fixed LRT threshold, not in the paper): entry (cell, row r) is a
+ * detection when its power exceeds alpha times the mean power of the same
+ * cell's rows r' with guard < |r' - r| <= guard + train inside [0, rows);
+ * the mean is a double-precision sum over r' in increasing order divided by
+ * the number of such rows, and an entry without any is never a detection.
+ * For exponentially distributed noise power and Nt = 2 train interior
+ * training rows, alpha = Nt (P_FA^(-1/Nt) - 1) gives false-alarm probability
+ * P_FA.  Map, cells, outputs and d_best as in dsgrft_detect; guard >= 0,
+ * 1 <= train, both <= 65536, alpha finite and >= 0, else E_INVALID. */
+dsgrft_status dsgrft_detect_cfar(dsgrft_plan plan, const float *d_pmax,
+                                 const int32_t *d_argf, const int64_t *d_cells,
+                                 int64_t cc_begin, int64_t n, int32_t guard,
+                                 int32_t train, double alpha, dsgrft_peak *d_peaks,
+                                 int32_t cap, int32_t *d_count, dsgrft_peak *d_best,
+                                 void *stream);
+
 /* Continuous objective for off-grid refinement (not in the paper; see the
  * oracle for the definition): for candidates theta[b] = (r0, v, a) (device
  * double [B][3]) computes Y_b (complex128) and J_b = |Y_b|^2 in FP64, and

@@ -87,6 +87,7 @@ def lib():
         "dsgrft_grft": [vp, vp, i64, i64, vp, vp, vp, vp],
         "dsgrft_noise_power": [vp, vp, vp, vp],
         "dsgrft_detect": [vp, vp, vp, vp, i64, i64, dbl, vp, i32, vp, vp, vp],
+        "dsgrft_detect_cfar": [vp, vp, vp, vp, i64, i64, i32, i32, dbl, vp, i32, vp, vp, vp],
         "dsgrft_adjoint_forward": [vp, vp, vp, i32, vp, vp, vp],
         "dsgrft_adjoint_backward": [vp, vp, vp, i32, vp, vp, vp, vp, vp],
         "dsgrft_refine": [vp, vp, vp, i32, i32, vp, vp],
@@ -115,6 +116,7 @@ def exported_symbols():
     return ["dsgrft_plan_create", "dsgrft_plan_destroy", "dsgrft_plan_get_info",
             "dsgrft_status_string", "dsgrft_coarse_tables", "dsgrft_mgift",
             "dsgrft_search", "dsgrft_search_full", "dsgrft_grft",
-            "dsgrft_noise_power", "dsgrft_detect", "dsgrft_adjoint_forward",
+            "dsgrft_noise_power", "dsgrft_detect", "dsgrft_detect_cfar",
+            "dsgrft_adjoint_forward",
             "dsgrft_adjoint_backward", "dsgrft_refine",
             "dsgrft_profile_begin", "dsgrft_profile_end"]

@@ -567,6 +567,23 @@ dsgrft_status dsgrft_detect(dsgrft_plan p, const float *d_pmax, const int32_t *d
   return DSGRFT_OK;
 }
 
+dsgrft_status dsgrft_detect_cfar(dsgrft_plan p, const float *d_pmax,
+                                 const int32_t *d_argf, const int64_t *d_cells,
+                                 int64_t cc_begin, int64_t n, int32_t guard, int32_t train,
+                                 double alpha, dsgrft_peak *d_peaks, int32_t cap,
+                                 int32_t *d_count, dsgrft_peak *d_best, void *stream) {
+  if (!p || !d_pmax || !d_argf || !d_count || n < 1 || cap < 0) return DSGRFT_E_INVALID;
+  if (cap > 0 && !d_peaks) return DSGRFT_E_INVALID;
+  if (guard < 0 || train < 1 || guard > 65536 || train > 65536) return DSGRFT_E_INVALID;
+  if (!std::isfinite(alpha) || alpha < 0.0) return DSGRFT_E_INVALID;
+  if (!d_cells && (cc_begin < 0 || cc_begin + n > p->n_coarse)) return DSGRFT_E_INVALID;
+  if (n > p->n_coarse || (double)n * p->rows > 2147483647.0) return DSGRFT_E_INVALID;
+  if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  DS_TRY(launch_detect_cfar(p, d_pmax, d_argf, d_cells, cc_begin, n, guard, train, alpha,
+                            d_peaks, cap, d_count, d_best, (hipStream_t)stream));
+  return DSGRFT_OK;
+}
+
 dsgrft_status dsgrft_adjoint_forward(dsgrft_plan p, const void *d_echo,
                                      const double *d_theta, int32_t B, double *d_J,
                                      double *d_saved, void *stream) {

@@ -5,6 +5,13 @@
 // best fine cell; parameters follow eq. (72) with kappa = 1 in FP64:
 // r0 = n0 dr, (v, a, j) = (coarse centre + fine offset) * fine step.
 //
+// The same kernels run a cell-averaging CFAR along range instead of the
+// fixed threshold (not in the paper): entry (cell, r) is a detection when its
+// power exceeds alpha times the mean of rows r' of the same cell with
+// guard < |r' - r| <= guard + train inside the map, the mean a float64 sum
+// in increasing r' divided by the number of those rows (no rows: no
+// detection).
+//
 // Deterministic ordered compaction in three kernels: per-chunk counts and
 // chunk maxima, one exclusive scan (and the global maximum, smallest flat
 // index on ties), then an ordered write per chunk.  A chunk is 4096 map
@@ -24,8 +31,38 @@ __device__ inline bool better(float v, int64_t i, float bv, int64_t bi) {
   return v > bv || (v == bv && i < bi);
 }
 
+// Detection tests on entry i of a reduced map.
+struct LrtTest {
+  double gamma2;
+  __device__ bool operator()(const float *__restrict__ pm, int64_t i) const {
+    return (double)pm[i] > gamma2;
+  }
+};
+
+struct CfarTest {
+  int rows, guard, train;
+  double alpha;
+  __device__ bool operator()(const float *__restrict__ pm, int64_t i) const {
+    const int64_t base = i - i % rows;
+    const int r = (int)(i - base);
+    const int lo = r - guard - train, hi = r + guard + train;
+    double sum = 0.0;
+    int cnt = 0;
+    for (int q = (lo > 0 ? lo : 0); q < r - guard; ++q) {
+      sum += (double)pm[base + q];
+      ++cnt;
+    }
+    for (int q = r + guard + 1; q <= hi && q < rows; ++q) {
+      sum += (double)pm[base + q];
+      ++cnt;
+    }
+    return cnt > 0 && (double)pm[i] > alpha * (sum / (double)cnt);
+  }
+};
+
+template <class Test>
 __global__ __launch_bounds__(TPB) void k_det_count(const float *__restrict__ pm,
-                                                   int64_t total, double gamma2,
+                                                   int64_t total, Test test,
                                                    int32_t *__restrict__ counts,
                                                    float *__restrict__ bv_out,
                                                    int64_t *__restrict__ bi_out) {
@@ -41,7 +78,7 @@ __global__ __launch_bounds__(TPB) void k_det_count(const float *__restrict__ pm,
     const int64_t i = base + tid + (int64_t)TPB * j;
     if (i < total) {
       const float v = pm[i];
-      cnt += ((double)v > gamma2) ? 1 : 0;
+      cnt += test(pm, i) ? 1 : 0;
       if (better(v, i, bv, bi)) {
         bv = v;
         bi = i;
@@ -161,9 +198,10 @@ __global__ __launch_bounds__(TPB) void k_det_scan(
   }
 }
 
+template <class Test>
 __global__ __launch_bounds__(TPB) void k_det_write(
     const float *__restrict__ pm, const int32_t *__restrict__ argf,
-    int64_t total, double gamma2, const int32_t *__restrict__ offsets,
+    int64_t total, Test test, const int32_t *__restrict__ offsets,
     PeakCtx ctx, dsgrft_peak *__restrict__ peaks, int32_t cap) {
   __shared__ int s_w[TPB / 64];
   const int64_t base = (int64_t)blockIdx.x * CHUNK;
@@ -171,7 +209,7 @@ __global__ __launch_bounds__(TPB) void k_det_write(
   int run = offsets[blockIdx.x];
   for (int j = 0; j < PER; ++j) {
     const int64_t i = base + tid + (int64_t)TPB * j;
-    const bool hit = (i < total) && ((double)pm[i] > gamma2);
+    const bool hit = (i < total) && test(pm, i);
     const unsigned long long mask = __ballot(hit);
     const int before = __popcll(mask & ((1ull << lane) - 1ull));
     if (lane == 0) s_w[wave] = __popcll(mask);
@@ -222,10 +260,13 @@ __global__ void k_noise_final(const double *__restrict__ part, int64_t nb, int64
 
 }  // namespace
 
-hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
-                         const int64_t *cells, int64_t cc_begin, int64_t n,
-                         double gamma2, dsgrft_peak *peaks, int32_t cap,
-                         int32_t *count, dsgrft_peak *best, hipStream_t s) {
+namespace {
+
+template <class Test>
+hipError_t launch_detect_t(dsgrft_plan p, const float *pmax, const int32_t *argf,
+                           const int64_t *cells, int64_t cc_begin, int64_t n, Test test,
+                           dsgrft_peak *peaks, int32_t cap, int32_t *count,
+                           dsgrft_peak *best, hipStream_t s) {
   const int64_t total = n * p->rows;
   const int64_t nch = (total + CHUNK - 1) / CHUNK;
   char *ws = (char *)p->det_ws;
@@ -235,13 +276,31 @@ hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
   PeakCtx ctx{cells, cc_begin, p->rows, p->n_begin, p->R, p->P, p->K[0], p->K[1],
               p->K[2], p->ilo[0], p->ilo[1], p->ilo[2], p->S0, p->dr,
               p->step[0], p->step[1], p->step[2]};
-  hipLaunchKernelGGL(k_det_count, dim3((unsigned)nch), dim3(TPB), 0, s, pmax, total,
-                     gamma2, counts, bv, bi);
+  hipLaunchKernelGGL(k_det_count<Test>, dim3((unsigned)nch), dim3(TPB), 0, s, pmax, total,
+                     test, counts, bv, bi);
   hipLaunchKernelGGL(k_det_scan, dim3(1), dim3(TPB), 0, s, counts, bv, bi, nch, pmax,
                      argf, ctx, count, best);
-  hipLaunchKernelGGL(k_det_write, dim3((unsigned)nch), dim3(TPB), 0, s, pmax, argf,
-                     total, gamma2, counts, ctx, peaks, cap);
+  hipLaunchKernelGGL(k_det_write<Test>, dim3((unsigned)nch), dim3(TPB), 0, s, pmax, argf,
+                     total, test, counts, ctx, peaks, cap);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
+                         const int64_t *cells, int64_t cc_begin, int64_t n,
+                         double gamma2, dsgrft_peak *peaks, int32_t cap,
+                         int32_t *count, dsgrft_peak *best, hipStream_t s) {
+  return launch_detect_t(p, pmax, argf, cells, cc_begin, n, LrtTest{gamma2}, peaks, cap,
+                         count, best, s);
+}
+
+hipError_t launch_detect_cfar(dsgrft_plan p, const float *pmax, const int32_t *argf,
+                              const int64_t *cells, int64_t cc_begin, int64_t n, int guard,
+                              int train, double alpha, dsgrft_peak *peaks, int32_t cap,
+                              int32_t *count, dsgrft_peak *best, hipStream_t s) {
+  return launch_detect_t(p, pmax, argf, cells, cc_begin, n,
+                         CfarTest{p->rows, guard, train, alpha}, peaks, cap, count, best, s);
 }
 
 size_t detect_ws_bytes(int64_t max_entries) {

@@ -205,6 +205,10 @@ hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
                          const int64_t *cells, int64_t cc_begin, int64_t n,
                          double gamma2, dsgrft_peak *peaks, int32_t cap,
                          int32_t *count, dsgrft_peak *best, hipStream_t s);
+hipError_t launch_detect_cfar(dsgrft_plan p, const float *pmax, const int32_t *argf,
+                              const int64_t *cells, int64_t cc_begin, int64_t n, int guard,
+                              int train, double alpha, dsgrft_peak *peaks, int32_t cap,
+                              int32_t *count, dsgrft_peak *best, hipStream_t s);
 hipError_t launch_adjoint_forward(dsgrft_plan p, const float2 *echo,
                                   const double *theta, int B, double *J,
                                   double *saved, hipStream_t s);

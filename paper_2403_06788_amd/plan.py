@@ -171,6 +171,23 @@ class Plan:
         bp = best.cpu().numpy().view(PEAK_DTYPE).reshape(-1)[0]
         return pk, cnt, bp
 
+    def detect_cfar(self, pmax, argf, guard, train, alpha, cap=1024, cells=None, cc_begin=0):
+        """Cell-averaging CFAR along range on a reduced map.  Returns (peaks
+        structured numpy array [min(count, cap)], count, best peak)."""
+        n = pmax.shape[0]
+        if cells is not None:
+            cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
+        peaks = torch.empty((max(cap, 1), PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+        best = torch.empty((1, PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+        count = torch.zeros(1, dtype=torch.int32, device="cuda")
+        check("dsgrft_detect_cfar", self._L.dsgrft_detect_cfar(
+            self._h, _ptr(pmax), _ptr(argf), _ptr(cells), cc_begin, n, int(guard), int(train),
+            float(alpha), _ptr(peaks), cap, _ptr(count), _ptr(best), _stream()))
+        cnt = int(count.item())
+        pk = peaks[:min(cnt, cap)].cpu().numpy().view(PEAK_DTYPE).reshape(-1)
+        bp = best.cpu().numpy().view(PEAK_DTYPE).reshape(-1)[0]
+        return pk, cnt, bp
+
     def threshold(self, sigma2, pfa):
         """gamma^2 = -M sigma^2 ln P_FA on |Y|^2."""
         return -self.M * float(sigma2) * float(np.log(pfa))

@@ -127,6 +127,7 @@ def test_null_pointers_rejected():
     assert L.dsgrft_plan_create(None, None, C.byref(h)) == 1
     assert L.dsgrft_search(None, 1, 1, None, None, 0, 1, None, None, None) == 1
     assert L.dsgrft_detect(None, None, None, None, 0, 1, 1.0, None, 0, None, None, None) == 1
+    assert L.dsgrft_detect_cfar(None, None, None, None, 0, 1, 2, 8, 5.0, None, 0, None, None, None) == 1
     assert L.dsgrft_adjoint_forward(None, None, None, 1, None, None, None) == 1
     info = _lib.PlanInfo()
     assert L.dsgrft_plan_get_info(None, C.byref(info)) == 1

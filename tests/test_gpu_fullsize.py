@@ -169,3 +169,18 @@ def test_config3_fft_form_sampled():
     _check_rows({c: pm[i] for c, i in idx.items()}, {c: af[i] for c, i in idx.items()},
                 case["echo"], grid, list(idx), rows, 1e-5)
     assert np.abs(pm - pm32).max() <= 2e-5 * pm32.max()
+
+
+def test_config3_cfar_on_full_map():
+    """CA-CFAR over the whole M=1024 reduced map (2460 cells x 4096 rows),
+    bit-exact against the oracle's CA-CFAR on the same map."""
+    from oracle import detect as OD
+    case, plan, grid, echo = _setup(3)
+    pm, af = plan.search(echo, "f16_3m", 1)
+    guard, train, alpha = 2, 16, 1.5
+    hit = OD.ca_cfar(pm.cpu().numpy(), guard, train, alpha)
+    cap = int(hit.sum()) + 16
+    peaks, cnt, _ = plan.detect_cfar(pm, af, guard, train, alpha, cap=cap)
+    assert cnt == int(hit.sum()) and len(peaks) == cnt
+    got = np.stack([peaks["coarse"].astype(np.int64), peaks["row"].astype(np.int64)], 1)
+    assert np.array_equal(got, np.argwhere(hit))
