@@ -330,6 +330,7 @@ def main():
         "roofline": roofline,
         "gather_roofline": gather,
         "cpu_baseline": cpu,
+        "paper_times": PAPER_TIMES,
         "speedup_vs_f32": round(value / f32_rate, 2),
         "rel_err": err,
         "detections": int(count),
@@ -350,6 +351,14 @@ def _sync():
 
 
 ADJ_FLOPS_PER_TAP = 20
+
+# The paper's own run times (Table IV): MATLAB on a CPU, for its Experiment 2
+# scenario, whose range-bin counts and grids it does not state, so they do not
+# convert to cells*pulses/s.  Reported beside the measurements as context.
+PAPER_TIMES = {"dsgrft_s": 141.7, "ds_kt_mfp_s": 41.1,
+               "hardware": "Intel Core i7-11700 (8 cores, 2.5 GHz), 32 GB, MATLAB 2019b",
+               "scenario": "fc 28 GHz, fs 491.52 MHz, PRF 1905 Hz, M=512, P=2 (Experiment 2)",
+               "comparable": False}
 
 
 def bench_adjoint(args):
@@ -598,6 +607,7 @@ def bench_kt(args):
            "gather_ms_per_step": round(prof["gather_ms"] / args.steps, 3),
            "fine_ms_per_step": round(prof["fine_ms"] / args.steps, 3),
            "cpu_baseline": None,
+           "paper_times": PAPER_TIMES,
            "cpu_baseline_note": "not measured: at this size the oracle's keystone alone takes "
                                 "minutes and each coarse cell's fine map ~1e11 complex MACs, "
                                 "so no bounded sample of the workload fits (the DS-GRFT line "
