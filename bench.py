@@ -234,8 +234,24 @@ def main():
               "bytes_per_launch": gather_bytes,
               "note": "elapsed time on the producer stream while the fine search of the "
                       "previous batch runs beside it (two-stream pipeline)"}
+    # the gather alone: one-batch searches, whose gather runs before any fine
+    # search is enqueued (nothing else on the GPU while it runs)
+    plan.profile_begin(64)
+    for _ in range(3):
+        torch.cuda.synchronize()
+        plan.search(echo, args.form, args.split, n=16, out=(pm[:16], af[:16]))
+    torch.cuda.synchronize()
+    p1 = plan.profile_end()
+    g1_s = p1["gather_ms"] / max(p1["gather_launches"], 1) * 1e-3
+    g1_b = p1["gather_bytes"] / max(p1["gather_launches"], 1)
+    gather_alone = {"bound": "hbm", "achieved": round(g1_b / g1_s / 1e9, 1), "peak": HBM_GBPS,
+                    "unit": "GB/s", "frac": round(g1_b / g1_s / 1e9 / HBM_GBPS, 4),
+                    "avg_launch_ms": round(g1_s * 1e3, 4), "bytes_per_launch": g1_b,
+                    "launches": p1["gather_launches"],
+                    "note": "one 16-cell batch at a time, nothing running beside it"}
     log(f"fine kernel: {achieved:.1f} TFLOP/s ({achieved / peak:.1%} of {peak}); "
-        f"gather {gather['achieved']:.0f} GB/s")
+        f"gather {gather['achieved']:.0f} GB/s beside the fine search, "
+        f"{gather_alone['achieved']:.0f} GB/s alone")
 
     # ---- accuracy on sampled rows vs the FP64 oracle ----------------------
     from oracle.grid import Axis, Radar, make_grid
@@ -329,6 +345,7 @@ def main():
                    "cells": cells * plan.rows * plan.n_fine, "pulses": plan.M},
         "roofline": roofline,
         "gather_roofline": gather,
+        "gather_roofline_alone": gather_alone,
         "cpu_baseline": cpu,
         "paper_times": PAPER_TIMES,
         "speedup_vs_f32": round(value / f32_rate, 2),
