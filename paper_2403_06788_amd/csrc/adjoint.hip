@@ -84,6 +84,22 @@ __device__ inline double recip(double d) {
   return fma(r, fma(-d, r, 1.0), r);
 }
 
+// 1/a, 1/b, 1/c, 1/d from one reciprocal (Montgomery's batch inversion):
+// with ab = a b, cd = c d and q = 1/(ab cd), 1/a = b cd q, 1/b = a cd q,
+// 1/c = d ab q, 1/d = c ab q; error a few FP64 ulps.  Callers pass
+// 1e-4 <= |x| < 2^24 for values at least 64 apart, so the product lies in
+// [40, 2^96], inside the normal range of recip's single-precision seed.
+__device__ inline void recip4(double a, double b, double c, double d, double &ra,
+                              double &rb, double &rc, double &rd) {
+  const double ab = a * b, cd = c * d;
+  const double q = recip(ab * cd);
+  const double qab = q * ab, qcd = q * cd;
+  ra = qcd * b;
+  rb = qcd * a;
+  rc = qab * d;
+  rd = qab * c;
+}
+
 // sinc(d) and d sinc(d)/dd near d = 0 (|d| < 1e-4), by their series.
 __device__ inline void sinc_series(double d, double &w, double &dw) {
   const double pd = M_PI * d;
@@ -140,6 +156,7 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
       // sin(pi (x - n)) = (-1)^(xi - n) sin(pi xf) is fixed per thread, and
       // d = x - n steps by exactly -64.
       double sr[CB], si[CB], dr_[CB], di[CB], A[CB], Bc[CB], d0[CB];
+      bool far_ok[CB];  // every |d| of the sweep below 2^24 (recip4's range)
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         sr[b] = si[b] = dr_[b] = di[b] = 0.0;
@@ -148,47 +165,63 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
         A[b] = sg * T.sp * (1.0 / M_PI);
         Bc[b] = sg * T.cp;
         d0[b] = (double)(T.xi - lane) + T.xf;
+        far_ok[b] = fabs(d0[b]) + (double)c.N + 256.0 < 16777216.0;
       }
-      // taps in pairs (n, n + 64) with separate accumulators, so that the
-      // two FMA chains per sum advance independently; summed after the sweep
+      // four taps (n, n + 64, n + 128, n + 192) per step, their reciprocals
+      // from one (recip4); taps 0, 2 and 1, 3 feed separate accumulators, so
+      // that two FMA chains per sum advance independently; summed after the
+      // sweep.  Taps at or beyond N carry a zero sample.
       double sr2[CB], si2[CB], dr2[CB], di2[CB];
 #pragma unroll
       for (int b = 0; b < CB; ++b) sr2[b] = si2[b] = dr2[b] = di2[b] = 0.0;
       int j = 0;
-      for (int n = lane; n < c.N; n += 128, j += 2) {
-        const float2 s0 = row[n];
-        const bool two = n + 64 < c.N;
-        const float2 s1 = two ? row[n + 64] : make_float2(0.f, 0.f);
-        const double sx0 = (double)s0.x, sy0 = (double)s0.y;
-        const double sx1 = (double)s1.x, sy1 = (double)s1.y;
+      for (int n = lane; n < c.N; n += 256, j += 4) {
+        double sx[4], sy[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const float2 v = (n + 64 * t < c.N) ? row[n + 64 * t] : make_float2(0.f, 0.f);
+          sx[t] = (double)v.x;
+          sy[t] = (double)v.y;
+        }
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
           if (b < nb) {
-            const double da = d0[b] - (double)(64 * j);
-            const double db = da - 64.0;
-            double wa, dwa, wb, dwb;
-            if (fabs(da) < 1e-4) {
-              sinc_series(da, wa, dwa);
+            double d[4], w[4], dw[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) d[t] = d0[b] - (double)(64 * (j + t));
+            const bool near0 = fabs(d[0]) < 1e-4 || fabs(d[1]) < 1e-4 ||
+                               fabs(d[2]) < 1e-4 || fabs(d[3]) < 1e-4;
+            if (!near0 && far_ok[b]) {
+              double r[4];
+              recip4(d[0], d[1], d[2], d[3], r[0], r[1], r[2], r[3]);
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                w[t] = A[b] * r[t];
+                dw[t] = (Bc[b] - w[t]) * r[t];
+              }
             } else {
-              const double r = recip(da);
-              wa = A[b] * r;
-              dwa = (Bc[b] - wa) * r;
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                if (fabs(d[t]) < 1e-4) {
+                  sinc_series(d[t], w[t], dw[t]);
+                } else {
+                  const double r = recip(d[t]);
+                  w[t] = A[b] * r;
+                  dw[t] = (Bc[b] - w[t]) * r;
+                }
+              }
             }
-            if (fabs(db) < 1e-4) {
-              sinc_series(db, wb, dwb);
-            } else {
-              const double r = recip(db);
-              wb = A[b] * r;
-              dwb = (Bc[b] - wb) * r;
+#pragma unroll
+            for (int t = 0; t < 4; t += 2) {
+              sr[b] = fma(sx[t], w[t], sr[b]);
+              si[b] = fma(sy[t], w[t], si[b]);
+              dr_[b] = fma(sx[t], dw[t], dr_[b]);
+              di[b] = fma(sy[t], dw[t], di[b]);
+              sr2[b] = fma(sx[t + 1], w[t + 1], sr2[b]);
+              si2[b] = fma(sy[t + 1], w[t + 1], si2[b]);
+              dr2[b] = fma(sx[t + 1], dw[t + 1], dr2[b]);
+              di2[b] = fma(sy[t + 1], dw[t + 1], di2[b]);
             }
-            sr[b] = fma(sx0, wa, sr[b]);
-            si[b] = fma(sy0, wa, si[b]);
-            dr_[b] = fma(sx0, dwa, dr_[b]);
-            di[b] = fma(sy0, dwa, di[b]);
-            sr2[b] = fma(sx1, wb, sr2[b]);
-            si2[b] = fma(sy1, wb, si2[b]);
-            dr2[b] = fma(sx1, dwb, dr2[b]);
-            di2[b] = fma(sy1, dwb, di2[b]);
           }
         }
       }
@@ -330,14 +363,34 @@ __global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__rest
       const double sg = ((q.xi - tid) & 1) ? -1.0 : 1.0;
       const double A = sg * q.sp * (1.0 / M_PI);
       const double d0 = (double)(q.xi - n0 - tid) + q.xf;
+      // reciprocals four at a time (recip4) unless a distance is near zero
+      // or the sweep leaves recip4's range
+      const bool far_ok = fabs(d0) + (double)(TPB * PER) < 16777216.0;
 #pragma unroll
-      for (int e = 0; e < PER; ++e) {
-        const double d = d0 - (double)(TPB * e);
-        double w, dw;
-        if (fabs(d) < 1e-4) sinc_series(d, w, dw);
-        else w = A * recip(d);
-        ar[e] = fma(w, q.cr, ar[e]);
-        ai[e] = fma(w, q.ci, ai[e]);
+      for (int e0 = 0; e0 < PER; e0 += 4) {
+        double d[4], w[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) d[t] = d0 - (double)(TPB * (e0 + t));
+        const bool near0 = fabs(d[0]) < 1e-4 || fabs(d[1]) < 1e-4 || fabs(d[2]) < 1e-4 ||
+                           fabs(d[3]) < 1e-4;
+        if (!near0 && far_ok) {
+          double r[4];
+          recip4(d[0], d[1], d[2], d[3], r[0], r[1], r[2], r[3]);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) w[t] = A * r[t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            double dw;
+            if (fabs(d[t]) < 1e-4) sinc_series(d[t], w[t], dw);
+            else w[t] = A * recip(d[t]);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          ar[e0 + t] = fma(w[t], q.cr, ar[e0 + t]);
+          ai[e0 + t] = fma(w[t], q.ci, ai[e0 + t]);
+        }
       }
     }
   }
