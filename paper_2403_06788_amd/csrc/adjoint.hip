@@ -174,15 +174,25 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
       double sr2[CB], si2[CB], dr2[CB], di2[CB];
 #pragma unroll
       for (int b = 0; b < CB; ++b) sr2[b] = si2[b] = dr2[b] = di2[b] = 0.0;
+      // Samples are loaded one step ahead from a clamped (always valid)
+      // index, and taps at or past N are zeroed where they are used, so that
+      // the four loads of a step are issued together and their latency
+      // overlaps the previous step's arithmetic.
+      auto load = [&](int nn) { return row[nn < c.N ? nn : c.N - 1]; };
+      float2 cur[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) cur[t] = load(lane + 64 * t);
       int j = 0;
       for (int n = lane; n < c.N; n += 256, j += 4) {
         double sx[4], sy[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-          const float2 v = (n + 64 * t < c.N) ? row[n + 64 * t] : make_float2(0.f, 0.f);
-          sx[t] = (double)v.x;
-          sy[t] = (double)v.y;
+          const bool in = n + 64 * t < c.N;
+          sx[t] = in ? (double)cur[t].x : 0.0;
+          sy[t] = in ? (double)cur[t].y : 0.0;
         }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cur[t] = load(n + 256 + 64 * t);
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
           if (b < nb) {
@@ -273,7 +283,7 @@ __device__ inline void finish(const AdjCtx &c, const double *o, double *sv) {
 }
 
 template <int CB>
-__global__ __launch_bounds__(TPB) void k_adj_fwd(AdjCtx c, const float2 *__restrict__ echo,
+__global__ __launch_bounds__(TPB, 3) void k_adj_fwd(AdjCtx c, const float2 *__restrict__ echo,
                                                  const double *__restrict__ theta, int B,
                                                  double *__restrict__ J,
                                                  double *__restrict__ saved) {
@@ -406,7 +416,7 @@ __global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__rest
 // radius is halved.  The fine indices stay inside the starting coarse cell,
 // r0 inside [0, N-1] bins.
 template <int CB>
-__global__ __launch_bounds__(TPB) void k_refine(AdjCtx c, const float2 *__restrict__ echo,
+__global__ __launch_bounds__(TPB, 3) void k_refine(AdjCtx c, const float2 *__restrict__ echo,
                                                 double *__restrict__ theta, int B, int iters,
                                                 double *__restrict__ Jout) {
   __shared__ Tap s_tap[TPB];
