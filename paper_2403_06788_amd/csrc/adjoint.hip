@@ -100,6 +100,18 @@ __device__ inline void recip4(double a, double b, double c, double d, double &ra
   rd = qab * c;
 }
 
+// A/a, A/b, A/c, A/d the same way, with A folded into the one reciprocal.
+__device__ inline void recip4_scaled(double A, double a, double b, double c, double d,
+                                     double &wa, double &wb, double &wc, double &wd) {
+  const double ab = a * b, cd = c * d;
+  const double q = A * recip(ab * cd);
+  const double qab = q * ab, qcd = q * cd;
+  wa = qcd * b;
+  wb = qcd * a;
+  wc = qab * d;
+  wd = qab * c;
+}
+
 // sinc(d) and d sinc(d)/dd near d = 0 (|d| < 1e-4), by their series.
 __device__ inline void sinc_series(double d, double &w, double &dw) {
   const double pd = M_PI * d;
@@ -155,8 +167,10 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
       // with the tap stride 64 even, the sign (-1)^(xi - n) of
       // sin(pi (x - n)) = (-1)^(xi - n) sin(pi xf) is fixed per thread, and
       // d = x - n steps by exactly -64.
-      double sr[CB], si[CB], dr_[CB], di[CB], A[CB], Bc[CB], d0[CB];
-      bool far_ok[CB];  // every |d| of the sweep below 2^24 (recip4's range)
+      double sr[CB], si[CB], dr_[CB], di[CB], A[CB], Bc[CB];
+      double dc[CB];     // d of this step's first tap, lowered by 256 per step
+      bool far_ok[CB];   // every |d| of the sweep below 2^24 (recip4's range)
+      int jnear[CB];     // the step j whose taps hold |d| < 1e-4, or -1
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         sr[b] = si[b] = dr_[b] = di[b] = 0.0;
@@ -164,8 +178,13 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
         const double sg = ((T.xi - lane) & 1) ? -1.0 : 1.0;
         A[b] = sg * T.sp * (1.0 / M_PI);
         Bc[b] = sg * T.cp;
-        d0[b] = (double)(T.xi - lane) + T.xf;
-        far_ok[b] = fabs(d0[b]) + (double)c.N + 256.0 < 16777216.0;
+        const double d0 = (double)(T.xi - lane) + T.xf;
+        dc[b] = d0;
+        far_ok[b] = fabs(d0) + (double)c.N + 256.0 < 16777216.0;
+        // taps are 64 apart, so only tap k = round(d0 / 64) can come within
+        // 1e-4 of zero; it sits in step j = 4 floor(k / 4)
+        const double ks = floor(d0 * (1.0 / 64.0) + 0.5);
+        jnear[b] = (ks >= 0.0 && ks < 1e9 && fabs(d0 - 64.0 * ks) < 1e-4) ? ((int)ks & ~3) : -1;
       }
       // four taps (n, n + 64, n + 128, n + 192) per step, their reciprocals
       // from one (recip4); taps 0, 2 and 1, 3 feed separate accumulators, so
@@ -196,12 +215,10 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
           if (b < nb) {
-            double d[4], w[4], dw[4];
+            double w[4], dw[4], d[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) d[t] = d0[b] - (double)(64 * (j + t));
-            const bool near0 = fabs(d[0]) < 1e-4 || fabs(d[1]) < 1e-4 ||
-                               fabs(d[2]) < 1e-4 || fabs(d[3]) < 1e-4;
-            if (!near0 && far_ok[b]) {
+            for (int t = 0; t < 4; ++t) d[t] = dc[b] - 64.0 * t;
+            if (j != jnear[b] && far_ok[b]) {
               double r[4];
               recip4(d[0], d[1], d[2], d[3], r[0], r[1], r[2], r[3]);
 #pragma unroll
@@ -232,6 +249,7 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
               dr2[b] = fma(sx[t + 1], dw[t + 1], dr2[b]);
               di2[b] = fma(sy[t + 1], dw[t + 1], di2[b]);
             }
+            dc[b] -= 256.0;
           }
         }
       }
@@ -373,21 +391,20 @@ __global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__rest
       const double sg = ((q.xi - tid) & 1) ? -1.0 : 1.0;
       const double A = sg * q.sp * (1.0 / M_PI);
       const double d0 = (double)(q.xi - n0 - tid) + q.xf;
-      // reciprocals four at a time (recip4) unless a distance is near zero
-      // or the sweep leaves recip4's range
+      // weights four at a time (recip4_scaled) unless the sweep leaves its
+      // range or the group holds the one output e = round(d0 / TPB) whose
+      // distance can come within 1e-4 of zero
       const bool far_ok = fabs(d0) + (double)(TPB * PER) < 16777216.0;
+      const double es = floor(d0 * (1.0 / TPB) + 0.5);
+      const int enear =
+          (es >= 0.0 && es < PER && fabs(d0 - TPB * es) < 1e-4) ? ((int)es & ~3) : -1;
 #pragma unroll
       for (int e0 = 0; e0 < PER; e0 += 4) {
         double d[4], w[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) d[t] = d0 - (double)(TPB * (e0 + t));
-        const bool near0 = fabs(d[0]) < 1e-4 || fabs(d[1]) < 1e-4 || fabs(d[2]) < 1e-4 ||
-                           fabs(d[3]) < 1e-4;
-        if (!near0 && far_ok) {
-          double r[4];
-          recip4(d[0], d[1], d[2], d[3], r[0], r[1], r[2], r[3]);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) w[t] = A * r[t];
+        if (e0 != enear && far_ok) {
+          recip4_scaled(A, d[0], d[1], d[2], d[3], w[0], w[1], w[2], w[3]);
         } else {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
