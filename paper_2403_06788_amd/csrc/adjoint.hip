@@ -193,25 +193,43 @@ __device__ void eval_block(const AdjCtx &c, const float2 *__restrict__ echo,
       double sr2[CB], si2[CB], dr2[CB], di2[CB];
 #pragma unroll
       for (int b = 0; b < CB; ++b) sr2[b] = si2[b] = dr2[b] = di2[b] = 0.0;
-      // Samples are loaded one step ahead from a clamped (always valid)
-      // index, and taps at or past N are zeroed where they are used, so that
-      // the four loads of a step are issued together and their latency
-      // overlaps the previous step's arithmetic.
+      // Samples are loaded one step ahead, so that the four loads of a step
+      // are issued together and their latency overlaps the previous step's
+      // arithmetic.  While every lane's four taps lie below N (a condition
+      // uniform over the wavefront) the loads are plain; near the end they
+      // come from a clamped (always valid) index and the taps at or past N
+      // are zeroed where they are used.
       auto load = [&](int nn) { return row[nn < c.N ? nn : c.N - 1]; };
+      auto all_in = [&](int n_lane0) { return n_lane0 + 63 + 192 < c.N; };
       float2 cur[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) cur[t] = load(lane + 64 * t);
       int j = 0;
       for (int n = lane; n < c.N; n += 256, j += 4) {
+        const int n_lane0 = n - lane;
         double sx[4], sy[4];
+        if (all_in(n_lane0)) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const bool in = n + 64 * t < c.N;
-          sx[t] = in ? (double)cur[t].x : 0.0;
-          sy[t] = in ? (double)cur[t].y : 0.0;
+          for (int t = 0; t < 4; ++t) {
+            sx[t] = (double)cur[t].x;
+            sy[t] = (double)cur[t].y;
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const bool in = n + 64 * t < c.N;
+            sx[t] = in ? (double)cur[t].x : 0.0;
+            sy[t] = in ? (double)cur[t].y : 0.0;
+          }
         }
+        if (all_in(n_lane0 + 256)) {
+          const float2 *nxt = row + n + 256;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) cur[t] = load(n + 256 + 64 * t);
+          for (int t = 0; t < 4; ++t) cur[t] = nxt[64 * t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) cur[t] = load(n + 256 + 64 * t);
+        }
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
           if (b < nb) {
