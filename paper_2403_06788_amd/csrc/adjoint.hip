@@ -367,21 +367,26 @@ struct BTap {  // per candidate for one pulse: sinc data and 2 gJ Y conj(e)
 };
 
 // grad_s[m][n] = sum_b sinc(x_bm - n) * (2 gJ_b Y_b conj(e_bm)).  One
-// workgroup per (pulse, 2048-bin slab); the candidate loop is chunked through
-// LDS.
-__global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__restrict__ theta,
-                                                  int B, const double *__restrict__ saved,
-                                                  const double *__restrict__ gJ,
-                                                  float2 *__restrict__ ge) {
-  __shared__ BTap s_b[TPB];
+// workgroup of 2 x 256 threads per (pulse, 2048-bin slab): each half sums
+// over its half of every 512-candidate chunk (staged in LDS) for the same
+// 2048 bins, and the halves' sums are added at the end (half 0 + half 1, a
+// fixed order); two halves double the waves per SIMD of a one-pulse grid.
+constexpr int ECHO_TPB = 2 * TPB;
+
+__global__ __launch_bounds__(ECHO_TPB) void k_adj_echo(AdjCtx c, const double *__restrict__ theta,
+                                                       int B, const double *__restrict__ saved,
+                                                       const double *__restrict__ gJ,
+                                                       float2 *__restrict__ ge) {
   constexpr int PER = 8;
+  __shared__ BTap s_b[ECHO_TPB];
+  __shared__ double s_part[2 * PER][TPB];
   const int slabs = (c.N + TPB * PER - 1) / (TPB * PER);
   const int m = blockIdx.x / slabs;
   const int n0 = (blockIdx.x % slabs) * TPB * PER;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, half = tid / TPB, t0 = tid % TPB;
   double ar[PER], ai[PER];
   for (int q = 0; q < PER; ++q) ar[q] = ai[q] = 0.0;
-  for (int bb = 0; bb < B; bb += TPB) {
+  for (int bb = 0; bb < B; bb += ECHO_TPB) {
     __syncthreads();
     const int b = bb + tid;
     if (b < B) {
@@ -402,13 +407,14 @@ __global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__rest
       s_b[tid] = q;
     }
     __syncthreads();
-    const int bend = (B - bb) < TPB ? (B - bb) : TPB;
-    for (int k = 0; k < bend; ++k) {
-      const BTap q = s_b[k];
-      // n = n0 + tid + TPB e with n0 and TPB even: fixed sign per thread
-      const double sg = ((q.xi - tid) & 1) ? -1.0 : 1.0;
+    const int kb = half * TPB;
+    const int kend = (B - bb - kb) < TPB ? (B - bb - kb) : TPB;
+    for (int k = 0; k < kend; ++k) {
+      const BTap q = s_b[kb + k];
+      // n = n0 + t0 + TPB e with n0 and TPB even: fixed sign per thread
+      const double sg = ((q.xi - t0) & 1) ? -1.0 : 1.0;
       const double A = sg * q.sp * (1.0 / M_PI);
-      const double d0 = (double)(q.xi - n0 - tid) + q.xf;
+      const double d0 = (double)(q.xi - n0 - t0) + q.xf;
       // weights four at a time (recip4_scaled) unless the sweep leaves its
       // range or the group holds the one output e = round(d0 / TPB) whose
       // distance can come within 1e-4 of zero
@@ -439,10 +445,21 @@ __global__ __launch_bounds__(TPB) void k_adj_echo(AdjCtx c, const double *__rest
       }
     }
   }
-  for (int e = 0; e < PER; ++e) {
-    const int n = n0 + tid + TPB * e;
-    if (n < c.N) ge[(int64_t)m * c.N + n] = make_float2((float)ar[e], (float)ai[e]);
-  }
+  __syncthreads();
+  if (half == 1)
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      s_part[2 * e][t0] = ar[e];
+      s_part[2 * e + 1][t0] = ai[e];
+    }
+  __syncthreads();
+  if (half == 0)
+    for (int e = 0; e < PER; ++e) {
+      const int n = n0 + t0 + TPB * e;
+      if (n < c.N)
+        ge[(int64_t)m * c.N + n] =
+            make_float2((float)(ar[e] + s_part[2 * e][t0]), (float)(ai[e] + s_part[2 * e + 1][t0]));
+    }
 }
 
 // Refinement: per candidate, normalised-gradient steps with a trust radius in
@@ -595,7 +612,7 @@ hipError_t launch_adjoint_backward(dsgrft_plan p, const float2 *echo,
                        B, grad_theta);
   if (grad_echo) {
     const int slabs = (p->N + TPB * 8 - 1) / (TPB * 8);
-    hipLaunchKernelGGL(k_adj_echo, dim3((unsigned)(p->M * slabs)), dim3(TPB), 0, s,
+    hipLaunchKernelGGL(k_adj_echo, dim3((unsigned)(p->M * slabs)), dim3(ECHO_TPB), 0, s,
                        make_ctx(p), theta, B, saved, gJ, grad_echo);
   }
   return hipGetLastError();
