@@ -272,7 +272,7 @@ def main():
     # ---- other forms: one warm step each ----------------------------------
     if not args.no_sweep:
         for form, split in (("f16_3m", 1), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4),
-                            ("bf16", 1), ("bf16", 2),
+                            ("bf16", 1), ("bf16", 2), ("bf16_glo", 2),
                             ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3),
                             ("fp8", 4), ("f32fft", 1)):
             if (form, split) == (args.form, args.split):

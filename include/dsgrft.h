@@ -80,11 +80,14 @@ typedef enum {
                               Alg. 2 (one per fine acceleration); split 1;
                               M a power of two in [64, 2048], else
                               E_UNSUPPORTED; the only form of DS-KT-MFP */
-  DSGRFT_FORM_F16_3M = 5   /* fp16, split 1, each complex product from three
+  DSGRFT_FORM_F16_3M = 5,  /* fp16, split 1, each complex product from three
                               real MFMA products (Gauss): P1 = Fr Gr,
                               P2 = Fi Gi, P3 = (Fr + Fi)(Gr + Gi) with the
                               sums rounded to fp16; Re = P1 - P2,
                               Im = P3 - P1 - P2 (FP32) */
+  DSGRFT_FORM_BF16_GLO = 6 /* bf16, split 2 only: Fh Gh + Fh Gl, the
+                              gathered rows split into hi + lo and the fine
+                              table not (the other order of split 2) */
 } dsgrft_form;
 
 typedef struct {
@@ -217,8 +220,8 @@ dsgrft_status dsgrft_mgift(dsgrft_plan plan, const void *d_echo,
  * give unspecified results but no access outside the plan's and the
  * caller's buffers) or, when d_cells is NULL,
  * cc_begin..cc_begin+n-1.  Outputs d_pmax, d_argf: [n][rows] (float, int32).
- * `form`/`split`: see dsgrft_form; FP32, FFT and F16_3M require split = 1
- * (else E_INVALID).  The echo must
+ * `form`/`split`: see dsgrft_form; FP32, FFT and F16_3M require split = 1,
+ * BF16_GLO split = 2 (else E_INVALID).  The echo must
  * stay unchanged until the stream reaches the end of this call. */
 dsgrft_status dsgrft_search(dsgrft_plan plan, dsgrft_form form, int32_t split,
                             const void *d_echo, const int64_t *d_cells,

@@ -62,8 +62,8 @@ bool on_plan_device(dsgrft_plan p) {
 
 dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
   if (p->kt && form != DSGRFT_FORM_F32_FFT)
-    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_F16_3M) ? DSGRFT_E_UNSUPPORTED
-                                                                  : DSGRFT_E_INVALID;
+    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_BF16_GLO) ? DSGRFT_E_UNSUPPORTED
+                                                                    : DSGRFT_E_INVALID;
   switch (form) {
     case DSGRFT_FORM_F32:
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
@@ -72,6 +72,8 @@ dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
       return p->fft_tw ? DSGRFT_OK : DSGRFT_E_UNSUPPORTED;
     case DSGRFT_FORM_F16_3M:
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
+    case DSGRFT_FORM_BF16_GLO:
+      return split == 2 ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_F16:
     case DSGRFT_FORM_BF16:
     case DSGRFT_FORM_FP8:
@@ -82,10 +84,10 @@ dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
 }
 
 // Bytes written per gathered sample: complex64, or 2 / 4 planes (lo parts
-// of G from split 3 on) of 2-byte or 1-byte components.
+// of G from split 3 on, and in BF16_GLO) of 2-byte or 1-byte components.
 double gather_bytes(dsgrft_form form, int split) {
   if (form == DSGRFT_FORM_F32 || form == DSGRFT_FORM_F32_FFT) return 8.0;
-  const double planes = split >= 3 ? 4.0 : 2.0;
+  const double planes = (split >= 3 || form == DSGRFT_FORM_BF16_GLO) ? 4.0 : 2.0;
   return planes * (form == DSGRFT_FORM_FP8 ? 1.0 : 2.0);
 }
 

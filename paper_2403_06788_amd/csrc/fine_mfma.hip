@@ -142,6 +142,14 @@ __device__ inline TileMap map_tile(int64_t bid, int64_t T, int NT, int FT, int G
   return tm;
 }
 
+// Product sets.  Split s (1..4) takes the first s of Fh Gh, Fl Gh, Fh Gl,
+// Fl Gl; SPLIT_GLO takes Fh Gh and Fh Gl (the gathered rows split, the fine
+// table not).
+constexpr int SPLIT_GLO = 5;
+constexpr int n_products(int split) { return split == SPLIT_GLO ? 2 : split; }
+constexpr bool f_lo(int split, int s) { return split != SPLIT_GLO && (s == 1 || s == 3); }
+constexpr bool g_lo(int split, int s) { return split == SPLIT_GLO ? s == 1 : s >= 2; }
+
 // Tile shape and pipeline depth per operand format and split count.  A
 // stage holds NPF planes x 4 fine fragments and NPG planes x 2 WNB row
 // fragments.  Two workgroups share a CU when their rings fit in 160 KiB
@@ -149,8 +157,8 @@ __device__ inline TileMap map_tile(int64_t bid, int64_t T, int NT, int FT, int G
 template <class Op, int SPLIT>
 struct Cfg {
   static constexpr int FR = Op::FR;
-  static constexpr int NPF = SPLIT >= 2 ? 4 : 2;  // fine-table planes
-  static constexpr int NPG = SPLIT >= 3 ? 4 : 2;  // gathered planes
+  static constexpr int NPF = (SPLIT >= 2 && SPLIT != SPLIT_GLO) ? 4 : 2;  // fine-table planes
+  static constexpr int NPG = SPLIT >= 3 ? 4 : 2;  // gathered planes (lo from split 3, GLO)
   static constexpr int WNB = FR == 1 ? 2 : 1;
   static constexpr int NBG = 2 * WNB;             // row fragments per plane
   static constexpr int NFRAG = NPF * 4 + NPG * NBG;
@@ -188,7 +196,7 @@ __device__ inline void wait_copies_barrier(int ahead) {
 template <class CF, int SPLIT>
 __device__ inline void order_step() {
   __builtin_amdgcn_sched_group_barrier(0x100, (CF::NPF * 2 + CF::NPG * CF::WNB) * CF::FR, 0);
-  __builtin_amdgcn_sched_group_barrier(0x008, SPLIT * 8 * CF::WNB, 0);
+  __builtin_amdgcn_sched_group_barrier(0x008, n_products(SPLIT) * 8 * CF::WNB, 0);
 }
 
 template <class CF>
@@ -243,9 +251,9 @@ __device__ inline void mma_step(const Frag<CF::FR> (&a)[CF::NPF][2],
                                 f16v (&accR)[2][CF::WNB], f16v (&accI)[2][CF::WNB],
                                 const int (&sa)[2], const int (&sb)[2][CF::WNB]) {
 #pragma unroll
-  for (int s = 0; s < SPLIT; ++s) {
-    const int la = (s == 1 || s == 3) ? 1 : 0;  // fine table lo in passes 1, 3
-    const int lb = (s >= 2) ? 1 : 0;            // gathered lo in passes 2, 3
+  for (int s = 0; s < n_products(SPLIT); ++s) {
+    const int la = f_lo(SPLIT, s) ? 1 : 0;  // fine table lo
+    const int lb = g_lo(SPLIT, s) ? 1 : 0;  // gathered lo
     const int pa = 2 * la, pb = 2 * lb;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -658,6 +666,9 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
     }
     case DSGRFT_FORM_BF16:
       return launch_split<OpBF16>(p, p->FBF16, 0, split, nunits, unit0, full, s);
+    case DSGRFT_FORM_BF16_GLO:
+      if (split != 2) return hipErrorInvalidValue;
+      return launch_t<OpBF16, SPLIT_GLO>(p, p->FBF16, 0, nunits, unit0, full, s);
     case DSGRFT_FORM_FP8:
       // fine table: hi = e4m3(256 F) -> 2^-8 (code 119), lo -> 2^-12
       return launch_split<OpF8>(p, p->F8, 119, split, nunits, unit0, full, s);
