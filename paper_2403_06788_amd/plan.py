@@ -110,7 +110,12 @@ class Plan:
     # ---- search -----------------------------------------------------------
     def search(self, echo, form="f16", split=1, cells=None, cc_begin=0, n=None,
                out=None):
-        """Reduced DS-GRFT map: (pmax [n, rows] float32, argf [n, rows] int32)."""
+        """Reduced DS-GRFT map: (pmax [n, rows] float32, argf [n, rows] int32).
+
+        form/split: "f32" (vector ALUs) and "f32fft" (slow-time FFT) with
+        split 1; "f16", "bf16", "fp8" with split 1-4 products; "f16_3m"
+        (three real products per complex product) with split 1; "bf16_glo"
+        (the gathered rows split) with split 2."""
         echo = _echo(echo)
         if cells is not None:
             cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
