@@ -452,12 +452,12 @@ __global__ __launch_bounds__(256, (Cfg<Op, SPLIT>::MINB)) void k_fine_mfma(
 // clock, so a quarter fewer matrix products is a quarter less of the energy
 // that sets it.
 //
-// Tile and ring as k_fine_mfma<OpF16, 1>: 128 fine x 128 rows per
-// workgroup, 64 x 64 per wave (2 x 2 blocks of 32x32x16), four LDS stages
-// of 16 KiB filled by LDS-DMA three steps ahead.  The three accumulator sets
-// take 192 registers, so there is no second fragment set: each step reads
-// its own fragments after the barrier, and the other workgroup's wave on
-// the same SIMD (two per CU) issues its MFMAs meanwhile.
+// Tile as k_fine_mfma<OpF16, 1>: 128 fine x 128 rows per workgroup, 64 x 64
+// per wave (2 x 2 blocks of 32x32x16); four LDS slots of 16 KiB filled by
+// LDS-DMA a pair of K steps ahead, one barrier per pair.  The three
+// accumulator sets take 192 registers, so there is no second fragment set:
+// each step reads its own fragments, and the other workgroup's wave on the
+// same SIMD (two per CU) issues its MFMAs meanwhile.
 __device__ inline uint4 add_h8(uint4 a, uint4 b) {
   return __builtin_bit_cast(uint4, __builtin_bit_cast(h8, a) + __builtin_bit_cast(h8, b));
 }
@@ -520,14 +520,8 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[q][i][j] = f16v{};
 
-  const int nkt = KS;
-#pragma unroll
-  for (int s = 0; s < NST - 1; ++s)
-    if (s < nkt) issue(s);
-  for (int kt = 0; kt < nkt; ++kt) {
-    // copies issued: stages 0 .. min(kt + NST - 2, nkt - 1); stage kt needed
-    const int left = nkt - 1 - kt;
-    wait_copies_barrier<CPT>(left < NST - 2 ? left : NST - 2);
+  // One K step: read the step's fragments, P1 and P2, the operand sums, P3.
+  auto step = [&](int kt) {
     const uint4 *slot = lds[kt % NST];
     uint4 fr[2], fi[2], gr[2], gi[2];
 #pragma unroll
@@ -538,9 +532,6 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
     for (int i = 0; i < 2; ++i) fi[i] = slot[(4 + wf * 2 + i) * 64 + lane];
 #pragma unroll
     for (int j = 0; j < 2; ++j) gi[j] = slot[(12 + wn * 2 + j) * 64 + lane];
-    // the slot of stage kt - 1: every wave has consumed it (its MFMAs of the
-    // previous step were issued before this barrier)
-    if (kt + NST - 1 < nkt) issue(kt + NST - 1);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -561,6 +552,23 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
 #pragma unroll
       for (int j = 0; j < 2; ++j)
         acc[2][i][j] = OpF16::mma({{fs[i]}}, {{gs[j]}}, acc[2][i][j], 0, 0);
+  };
+
+  // Steps go in pairs (KS is a multiple of 4), one barrier per pair: the
+  // pair (kt, kt + 1) waits for its own copies, and the next pair is copied
+  // into the slots of the previous one, which every wave finished before
+  // this barrier.
+  const int nkt = KS;
+  issue(0);
+  issue(1);
+  for (int kt = 0; kt < nkt; kt += 2) {
+    wait_copies_barrier<CPT>(0);
+    if (kt + 2 < nkt) {
+      issue(kt + 2);
+      issue(kt + 3);
+    }
+    step(kt);
+    step(kt + 1);
   }
 
   // ---- epilogue as in k_fine_mfma ----------------------------------------
@@ -657,7 +665,8 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
     case DSGRFT_FORM_F16:
       return launch_split<OpF16>(p, p->F16, 0, split, nunits, unit0, full, s);
     case DSGRFT_FORM_F16_3M: {
-      if (split != 1) return hipErrorInvalidValue;
+      // K steps go in pairs: Mp is a multiple of 64, so Mp / 16 is even
+      if (split != 1 || (p->Mp / OpF16::KSTEP) % 2 != 0) return hipErrorInvalidValue;
       const int64_t tiles = nunits * (p->NB / 4) * (p->FB / 4);
       hipLaunchKernelGGL(k_fine_mfma3, dim3((unsigned)tiles), dim3(256), 0, s,
                          (const uint4 *)p->F16, (const uint4 *)p->G, p->packed, full, p->FB,
