@@ -122,8 +122,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for rocprofv3 counter passes")
-    ap.add_argument("--workload", type=int, default=3, choices=(3, 4, 5, 6, 7),
-                    help="3: the M=1024 search (default, headline metric); "
+    ap.add_argument("--workload", type=int, default=3, choices=(2, 3, 4, 5, 6, 7),
+                    help="2: single-scale TD-GRFT against DS-GRFT at M=512; "
+                         "3: the M=1024 search (default, headline metric); "
                          "4: adjoint at M=512; 5: third-order search at M=2048 "
                          "on a 64-coarse-cell subset; 6: Monte-Carlo detection "
                          "probability vs SNR (M=256); 7: DS-KT-MFP search on the "
@@ -144,6 +145,8 @@ def main():
     import synth
     from paper_2403_06788_amd.plan import Plan
 
+    if args.workload == 2:
+        return bench_grft(args)
     if args.workload == 4:
         return bench_adjoint(args)
     if args.workload == 5:
@@ -488,6 +491,59 @@ def bench_adjoint(args):
                                            "a_mps2": float(errs[:, 2].max())},
                       "fine_steps": {"dr_m": plan.dr, "dv_mps": plan.step[0],
                                      "da_mps2": plan.step[1]}}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_grft(args):
+    """M=512, N=2048, P=2 (v +-600 m/s, a +-50 m/s^2): the single-scale
+    TD-GRFT (eq. (13), every lattice point on its own walk) against DS-GRFT
+    on the same echo and lattice, whose cells it matches one to one."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2403_06788_amd.plan import Plan
+    case = synth.config_case(2)
+    c = synth.CONFIGS[2]
+    r = c["radar"]
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"])
+    echo = torch.from_numpy(case["echo"]).cuda()
+    n = plan.n_coarse
+    cp_cell = float(plan.rows) * plan.n_fine * plan.M
+    res = {}
+
+    def timed(fn, ncells, key):
+        fn(min(ncells, 2))
+        _sync()
+        t0 = time.perf_counter()
+        out = fn(ncells)
+        _sync()
+        dt = time.perf_counter() - t0
+        res[key] = {"cells_pulses_per_s": ncells * cp_cell / dt, "s": round(dt, 4),
+                    "coarse_cells": ncells}
+        log(f"{key}: {ncells} coarse cells in {dt:.3f} s, {ncells * cp_cell / dt:.3e} cells*pulses/s")
+        return out
+    pm_ds, _ = timed(lambda k: plan.search(echo, "f16_3m", 1, n=k), n, "dsgrft_f16_3mx1")
+    pm_32, _ = timed(lambda k: plan.search(echo, "f32", 1, n=k), min(n, 32), "dsgrft_f32x1")
+    ng = min(n, 32)
+    pm_g, _ = timed(lambda k: plan.grft(echo, 0, k), ng, "grft_f32")
+    # the two transforms differ where the fine walk leaves the coarse walk's
+    # bin; compare their per-(cell, row) maxima on the GRFT sample
+    a, b = pm_g.cpu().numpy().astype(np.float64), pm_32[:ng].cpu().numpy().astype(np.float64)
+    out = {"metric": "TD-GRFT and DS-GRFT cells·pulses/s (M=512, P=2)",
+           "value": res["dsgrft_f16_3mx1"]["cells_pulses_per_s"], "unit": "cells·pulses/s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
+           "config": {"workload": "M=512 pulses, N=2048 bins, P=2 (v +-600 m/s, a +-50 m/s^2), "
+                                  f"{n} coarse x {plan.n_fine} fine cells x {plan.rows} rows, "
+                                  "3 targets at -15 dB",
+                      "cells": n * plan.rows * plan.n_fine, "pulses": plan.M},
+           "forms": res,
+           "speedup_dsgrft_vs_grft": {
+               "f16_3mx1": res["dsgrft_f16_3mx1"]["cells_pulses_per_s"] / res["grft_f32"]["cells_pulses_per_s"],
+               "f32x1": res["dsgrft_f32x1"]["cells_pulses_per_s"] / res["grft_f32"]["cells_pulses_per_s"]},
+           "reduced_map_ds_over_grft": {"max_ratio": float(b.max() / a.max()),
+                                        "median_ratio": float(np.median(b / np.maximum(a, 1e-30)))}}
     print(json.dumps(out), flush=True)
 
 
