@@ -36,6 +36,8 @@ namespace {
 using fftreg::cmulf;
 using fftlds::TwLds;
 using fftlds::fft_lds;
+using fftlds::fft_lds_io;
+using fftlds::first_radix;
 using fftlds::load_twiddles;
 using fftlds::lds_len;
 using fftlds::pidx;
@@ -142,22 +144,23 @@ __global__ __launch_bounds__(256) void k_kt_shift(
   const int64_t num2 = i2c * m * m;
   const int64_t xi2 = floor_div(num2, RM2);
   const double xf2 = (double)(num2 - xi2 * RM2) / (double)RM2;
+  // the first pass's elements straight from the spectrum (thread j < NP / R1
+  // takes k = j + t NP / R1, coalesced over j); the FP64 reciprocals in
+  // groups of LB, all of a group's loads issued before the first is used
+  constexpr int R1 = first_radix<NP>(), NG1 = NP / R1, LB = R1 < 8 ? R1 : 8;
   const float2 *sp = kspec + (int64_t)m * NP;
-  // loads in groups of LB per thread, all issued before the first is used
-  constexpr int EPT = (NP + 255) / 256, LB = EPT < 16 ? EPT : 16;
-  for (int e0 = 0; e0 < EPT; e0 += LB) {
-    float2 sv[LB];
-    double iv[LB];
+  float2 v[R1];
+  if (tid < NG1) {
 #pragma unroll
-    for (int e = 0; e < LB; ++e) {
-      const int kk = tid + 256 * (e0 + e);
-      sv[e] = kk < NP ? sp[kk] : make_float2(0.f, 0.f);
-      iv[e] = kk < NP ? invd[kk] : 0.0;
-    }
+    for (int t = 0; t < R1; ++t) v[t] = sp[tid + t * NG1];
 #pragma unroll
-    for (int e = 0; e < LB; ++e) {
-      const int kk = tid + 256 * (e0 + e);
-      if (kk < NP) {
+    for (int t0 = 0; t0 < R1; t0 += LB) {
+      double iv[LB];
+#pragma unroll
+      for (int e = 0; e < LB; ++e) iv[e] = invd[tid + (t0 + e) * NG1];
+#pragma unroll
+      for (int e = 0; e < LB; ++e) {
+        const int kk = tid + (t0 + e) * NG1;
         const int ks = kk < NP / 2 ? kk : kk - NP;
         const int ii = (int)(((int64_t)ks * xi2) & (NP - 1));   // (k_s xi2) mod NP
         double turns = g * (double)ks * iv[e] -
@@ -165,18 +168,21 @@ __global__ __launch_bounds__(256) void k_kt_shift(
         turns -= rint(turns);
         float s, c;
         sincospif(2.0f * (float)turns, &s, &c);
-        X[pidx(kk)] = cmulf(sv[e], make_float2(c, s));
+        v[t0 + e] = cmulf(v[t0 + e], make_float2(c, s));
       }
     }
   }
-  __syncthreads();
-  fft_lds<NP, 1, true>(X, tl);
+  // outputs n_begin + r straight to the unit's row; rows from rows to rows_p
+  // are zero (those past the transform's end below)
   const float inv = 1.0f / (float)NP;
   float2 *o = E + ((int64_t)u * M + m) * rows_p;
-  for (int r = tid; r < rows_p; r += 256) {
-    const float2 y = X[pidx(n_begin + r < NP ? n_begin + r : 0)];
-    o[r] = (r < rows) ? make_float2(y.x * inv, y.y * inv) : make_float2(0.f, 0.f);
-  }
+  fft_lds_io<NP, true>(v, X, tl, [&](int i, float2 y) {
+    const int r = i - n_begin;
+    if (r >= 0 && r < rows_p)
+      o[r] = (r < rows) ? make_float2(y.x * inv, y.y * inv) : make_float2(0.f, 0.f);
+  });
+  for (int r = (NP - n_begin > 0 ? NP - n_begin : 0) + tid; r < rows_p; r += 256)
+    o[r] = make_float2(0.f, 0.f);
 }
 
 template <int M>

@@ -28,6 +28,8 @@ namespace {
 using fftreg::cmulf;
 using fftlds::TwLds;
 using fftlds::fft_lds;
+using fftlds::fft_lds_io;
+using fftlds::first_radix;
 using fftlds::load_twiddles;
 using fftlds::lds_len;
 using fftlds::pidx;
@@ -94,35 +96,36 @@ __global__ __launch_bounds__(256) void k_fd_shift(
     else TC[i - NA] = make_float2(c, s);
   }
   __syncthreads();
+  // the first pass's elements straight from the spectrum (thread j < NP / R1
+  // takes k = j + t NP / R1, coalesced over j), all loads issued before the
+  // first is used
+  constexpr int R1 = first_radix<NP>(), NG1 = NP / R1;
   const float2 *sp = spec + (int64_t)m * NP;
-  constexpr int EPT = (NP + 255) / 256, LB = EPT < 16 ? EPT : 16;
-  for (int e0 = 0; e0 < EPT; e0 += LB) {
-    float2 sv[LB];
+  float2 v[R1];
+  if (tid < NG1) {
 #pragma unroll
-    for (int e = 0; e < LB; ++e) {
-      const int kk = tid + 256 * (e0 + e);
-      sv[e] = kk < NP ? sp[kk] : make_float2(0.f, 0.f);
-    }
+    for (int t = 0; t < R1; ++t) v[t] = sp[tid + t * NG1];
 #pragma unroll
-    for (int e = 0; e < LB; ++e) {
-      const int kk = tid + 256 * (e0 + e);
-      if (kk < NP) {
-        const int ks = kk < NP / 2 ? kk : kk - NP;
-        const int ii = (int)(((int64_t)ks * xi) & (NP - 1));  // (k_s xi) mod NP
-        const int a = ks >> 6, c = ks & 63;                    // k_s = 64 a + c
-        const float2 w = cmulf(cmulf(tl(ii), TA[a + A0]), TC[c]);
-        X[pidx(kk)] = cmulf(sv[e], w);
-      }
+    for (int t = 0; t < R1; ++t) {
+      const int kk = tid + t * NG1;
+      const int ks = kk < NP / 2 ? kk : kk - NP;
+      const int ii = (int)(((int64_t)ks * xi) & (NP - 1));  // (k_s xi) mod NP
+      const int a = ks >> 6, c = ks & 63;                    // k_s = 64 a + c
+      const float2 w = cmulf(cmulf(tl(ii), TA[a + A0]), TC[c]);
+      v[t] = cmulf(v[t], w);
     }
   }
-  __syncthreads();
-  fft_lds<NP, 1, true>(X, tl);
+  // outputs n_begin + r straight to the unit's row; rows from rows to rows_p
+  // are zero (those past the transform's end below)
   const float inv = 1.0f / (float)NP;
   float2 *out = E + ((int64_t)u * M + m) * rows_p;
-  for (int r = tid; r < rows_p; r += 256) {
-    const float2 y = X[pidx(n_begin + r < NP ? n_begin + r : 0)];
-    out[r] = (r < rows) ? make_float2(y.x * inv, y.y * inv) : make_float2(0.f, 0.f);
-  }
+  fft_lds_io<NP, true>(v, X, tl, [&](int i, float2 y) {
+    const int r = i - n_begin;
+    if (r >= 0 && r < rows_p)
+      out[r] = (r < rows) ? make_float2(y.x * inv, y.y * inv) : make_float2(0.f, 0.f);
+  });
+  for (int r = (NP - n_begin > 0 ? NP - n_begin : 0) + tid; r < rows_p; r += 256)
+    out[r] = make_float2(0.f, 0.f);
 }
 
 __global__ void k_fd_twiddles(int NP, float2 *tw) {
