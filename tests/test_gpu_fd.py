@@ -79,6 +79,31 @@ def test_fd_equals_td_on_integer_walks():
     assert np.abs(yfd[1] - ref).max() <= 1e-5 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("Np", [64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384])
+def test_fd_mgift_rows_every_transform_length(Np):
+    """Every length of the shift's range IFFT (N' = 64 ... 16384, each with
+    its own radix plan, first pass on the loaded spectrum and last pass
+    straight to the rows) against the oracle, on a row window that starts
+    inside the row and ends before N."""
+    from paper_2403_06788_amd.plan import Plan
+    r = Radar(2.0e7, 1.0e7, 100.0)
+    M, N = 8, Np * 3 // 4
+    dv = make_grid(r, M, N, 1, [Axis(0.0, 0.0)]).steps[0]
+    axes = [(15 * dv, 18 * dv)]
+    n_begin, n_end = N // 4 + 3, N - 5
+    g = make_grid(r, M, N, 1, [Axis(*axes[0])], n_begin, n_end)
+    assert OF.pad_length(g) == Np
+    rng = np.random.default_rng(Np)
+    e = (rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))).astype(np.complex64)
+    p = Plan(2.0e7, 1.0e7, 100.0, M, N, 1, axes, rows=(n_begin, n_end), mgift="fd")
+    assert p.fd_pad == Np
+    y = p.mgift(torch.from_numpy(e).cuda()).cpu().numpy()
+    S = OF.range_spectrum(e, Np)
+    ref = np.stack([OF.mgift_fd(e, g, k, Np, S) for k in range(g.n_coarse)])
+    assert y.shape == ref.shape
+    assert np.abs(y - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
 def test_fd_config3_sampled_rows():
     """M = 1024, N = 4096 (N' = 8192) in the benchmark's batching: f16 x1 on
     two cells, sampled rows against the frequency-domain oracle."""
