@@ -11,10 +11,11 @@
 //                                   exp(+j 2 pi k (n_begin + r) / NP),
 //    with k_s the signed frequency index (k, or k - NP from NP/2 on) and
 //    x(m) = Num_c(m) / (R M^3) the coarse walk of the unit's cell in bins.
-//    The phase k_s x / NP is formed as ((k_s xi) mod NP) / NP + k_s xf / NP
-//    with xi = floor(x) exact and xf in [0, 1) in FP64; the second factor is
-//    a product of two small tables (k_s = 64 a + c) whose phases are reduced
-//    in FP64.
+//    A turn count n x / NP is formed as ((n xi) mod NP) / NP + n xf / NP
+//    with xi = floor(x) exact and xf in [0, 1) in FP64.  The thread that
+//    loads k = j + t NP/R1 (the FFT's first pass) takes the ramp as the
+//    product of exp(+j 2 pi j x / NP), its own, and exp(+j 2 pi (k_s - j) x
+//    / NP), one of R1 per workgroup.
 // The rows E[u] then go through the ordinary gathers with zero offsets, which
 // apply the pre-DFM phase (eq. (47)) and write the fine search's layout.
 //
@@ -68,10 +69,9 @@ __global__ __launch_bounds__(256) void k_fd_shift(
     const int64_t *cells, int64_t cc_base, int64_t unit0, int M, int R3, int R,
     int P, int K0, int K1, int K2, int i0, int i1, int i2, Lat L, int rows,
     int rows_p, int n_begin, float2 *__restrict__ E) {
+  constexpr int R1 = first_radix<NP>(), NG1 = NP / R1;
   __shared__ float2 X[lds_len<NP>()];
-  constexpr int A0 = (NP + 127) / 128;            // -min(a), k_s = 64 a + c
-  constexpr int NA = NP / 64 > 2 ? NP / 64 : 2;
-  __shared__ float2 TA[NA], TC[64];
+  __shared__ float2 TP[R1];
   __shared__ float2 t_lo[128], t_hi[NP / 128 > 1 ? NP / 128 : 1];
   const TwLds tl = load_twiddles<NP>(tw, t_lo, t_hi);
   const int tid = threadIdx.x;
@@ -85,35 +85,30 @@ __global__ __launch_bounds__(256) void k_fd_shift(
   const int64_t num = lat_num(L, m, ic[0], ic[1], ic[2]);
   const int64_t xi = floor_div(num, L.RM3);
   const double xf = (double)(num - xi * L.RM3) / (double)L.RM3;
-  // sub-ramp factors: the turn fractions (|.| <= 1/2) are formed in FP64 and
-  // their sine and cosine taken in FP32 (error ~ FP32 rounding of the result)
-  for (int i = tid; i < NA + 64; i += 256) {
-    const double turns = (i < NA) ? 64.0 * (double)(i - A0) * xf / NP
-                                  : (double)(i - NA) * xf / NP;
+  // exp(+j 2 pi n x / NP): the turns reduced in FP64 (|.| <= 1/2), their
+  // sine and cosine in FP32 (error ~ FP32 rounding of the result)
+  auto ramp = [&](int64_t n) {
+    const int64_t ii = (n * xi) & (NP - 1);  // (n xi) mod NP, n xi exact
+    double turns = ((double)ii + (double)n * xf) / (double)NP;
+    turns -= rint(turns);
     float s, c;
     sincospif(2.0f * (float)turns, &s, &c);
-    if (i < NA) TA[i] = make_float2(c, s);
-    else TC[i - NA] = make_float2(c, s);
-  }
+    return make_float2(c, s);
+  };
+  // k = j + t NG1 has k_s - j = t NG1, less NP from t = R1 / 2 on
+  if (tid < R1) TP[tid] = ramp((int64_t)tid * NG1 - (tid >= R1 / 2 ? NP : 0));
+  const float2 rj = ramp(tid);
   __syncthreads();
   // the first pass's elements straight from the spectrum (thread j < NP / R1
   // takes k = j + t NP / R1, coalesced over j), all loads issued before the
   // first is used
-  constexpr int R1 = first_radix<NP>(), NG1 = NP / R1;
   const float2 *sp = spec + (int64_t)m * NP;
   float2 v[R1];
   if (tid < NG1) {
 #pragma unroll
     for (int t = 0; t < R1; ++t) v[t] = sp[tid + t * NG1];
 #pragma unroll
-    for (int t = 0; t < R1; ++t) {
-      const int kk = tid + t * NG1;
-      const int ks = kk < NP / 2 ? kk : kk - NP;
-      const int ii = (int)(((int64_t)ks * xi) & (NP - 1));  // (k_s xi) mod NP
-      const int a = ks >> 6, c = ks & 63;                    // k_s = 64 a + c
-      const float2 w = cmulf(cmulf(tl(ii), TA[a + A0]), TC[c]);
-      v[t] = cmulf(v[t], w);
-    }
+    for (int t = 0; t < R1; ++t) v[t] = cmulf(v[t], cmulf(rj, TP[t]));
   }
   // outputs n_begin + r straight to the unit's row; rows from rows to rows_p
   // are zero (those past the transform's end below)
