@@ -23,12 +23,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DS-GRFT cells·pulses/s (M=1024); MFMA vs FP32 speedup at rel err≤1e-3"
-PEAK_TFLOPS = {"f16": 2500.0, "f16_3m": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3,
+PEAK_TFLOPS = {"f16": 2500.0, "f16_3m": 2500.0, "f16_sym": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3,
                "f32fft": 157.3}
-DTYPE = {"f16_3m": "f16", "f32fft": "f32"}
-KERNEL = {"f16_3m": "k_fine_mfma3 (f16, three real products per complex product)"}
+DTYPE = {"f16_3m": "f16", "f16_sym": "f16", "f32fft": "f32"}
+KERNEL = {"f16_3m": "k_fine_mfma3 (f16, three real products per complex product)",
+          "f16_sym": "k_fine_mfma_sym (f16, fine cells in conjugate pairs, four real products per pair)"}
 FORM_TEXT = {"f16_3m": "f16 MFMA, three real products per complex product (Gauss), split 1, "
                        "FP32 accumulation",
+             "f16_sym": "f16 MFMA, fine cells in conjugate pairs (four real products for the "
+                        "cells at +d and -d), split 1, FP32 accumulation",
              "f32fft": "FP32, fine velocities by slow-time FFT"}
 HBM_GBPS = 8000.0
 FINE_SRC = os.path.join(ROOT, "paper_2403_06788_amd", "csrc", "fine_mfma.hip")
@@ -275,7 +278,7 @@ def main():
                                          "argmax_checked": clear}
     # ---- other forms: one warm step each ----------------------------------
     if not args.no_sweep:
-        for form, split in (("f16_3m", 1), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4),
+        for form, split in (("f16_sym", 1), ("f16_3m", 1), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4),
                             ("bf16", 1), ("bf16", 2), ("bf16_glo", 2),
                             ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3),
                             ("fp8", 4), ("f32fft", 1)):
@@ -575,7 +578,7 @@ def bench_jerk(args):
     n = cells.numel()
     cp = float(n) * plan.rows * plan.n_fine * plan.M
     res = {}
-    for form, split in (("f16_3m", 1), ("f16", 1), ("bf16", 1), ("bf16", 3)):
+    for form, split in (("f16_sym", 1), ("f16_3m", 1), ("f16", 1), ("bf16", 1), ("bf16", 3)):
         plan.search(echo, form, split, cells=cells[:1])
         _sync()
         t0 = time.perf_counter()

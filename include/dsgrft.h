@@ -85,9 +85,18 @@ typedef enum {
                               P2 = Fi Gi, P3 = (Fr + Fi)(Gr + Gi) with the
                               sums rounded to fp16; Re = P1 - P2,
                               Im = P3 - P1 - P2 (FP32) */
-  DSGRFT_FORM_BF16_GLO = 6 /* bf16, split 2 only: Fh Gh + Fh Gl, the
+  DSGRFT_FORM_BF16_GLO = 6, /* bf16, split 2 only: Fh Gh + Fh Gl, the
                               gathered rows split into hi + lo and the fine
                               table not (the other order of split 2) */
+  DSGRFT_FORM_F16_SYM = 7  /* fp16, split 1, the fine cells taken in
+                              conjugate pairs: the fine offsets are symmetric
+                              about the coarse centre and the fine phase
+                              (eq. (44)) is linear in them, so the cell at
+                              -d has the conjugate phasor of the cell at +d;
+                              the four real products Fr Gr, Fi Gi, Fr Gi,
+                              Fi Gr of the +d column give both cells.  Same
+                              operands and rounding as F16 split 1; not for
+                              DS-KT-MFP plans */
 } dsgrft_form;
 
 typedef struct {
@@ -220,7 +229,7 @@ dsgrft_status dsgrft_mgift(dsgrft_plan plan, const void *d_echo,
  * give unspecified results but no access outside the plan's and the
  * caller's buffers) or, when d_cells is NULL,
  * cc_begin..cc_begin+n-1.  Outputs d_pmax, d_argf: [n][rows] (float, int32).
- * `form`/`split`: see dsgrft_form; FP32, FFT and F16_3M require split = 1,
+ * `form`/`split`: see dsgrft_form; FP32, FFT, F16_3M and F16_SYM require split = 1,
  * BF16_GLO split = 2 (else E_INVALID).  The echo must
  * stay unchanged until the stream reaches the end of this call. */
 dsgrft_status dsgrft_search(dsgrft_plan plan, dsgrft_form form, int32_t split,

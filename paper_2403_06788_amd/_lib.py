@@ -18,7 +18,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory",
           3: "HIP runtime error", 4: "unsupported request",
           5: "output capacity exceeded"}
 
-FORMS = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "f32fft": 4, "f16_3m": 5, "bf16_glo": 6}
+FORMS = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "f32fft": 4, "f16_3m": 5, "bf16_glo": 6, "f16_sym": 7}
 
 
 class DsgrftError(RuntimeError):

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "internal.h"
 
@@ -43,7 +44,7 @@ hipError_t dalloc(T **p, size_t bytes, size_t &total) {
 
 void release(dsgrft_plan p) {
   if (!p) return;
-  void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->u_off, p->u_psi,
+  void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->FS16, p->sym_cols, p->u_off, p->u_psi,
                   p->Gbuf[0], p->gscbuf[0], p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
                   p->kt_spec, p->kt_invd, p->packed, p->det_ws, p->adj_ws};
   for (void *b : bufs)
@@ -62,7 +63,7 @@ bool on_plan_device(dsgrft_plan p) {
 
 dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
   if (p->kt && form != DSGRFT_FORM_F32_FFT)
-    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_BF16_GLO) ? DSGRFT_E_UNSUPPORTED
+    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_F16_SYM) ? DSGRFT_E_UNSUPPORTED
                                                                     : DSGRFT_E_INVALID;
   switch (form) {
     case DSGRFT_FORM_F32:
@@ -71,6 +72,7 @@ dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
       if (split != 1) return DSGRFT_E_INVALID;
       return p->fft_tw ? DSGRFT_OK : DSGRFT_E_UNSUPPORTED;
     case DSGRFT_FORM_F16_3M:
+    case DSGRFT_FORM_F16_SYM:
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_BF16_GLO:
       return split == 2 ? DSGRFT_OK : DSGRFT_E_INVALID;
@@ -175,6 +177,24 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
 // Zero-padded range-FFT length of the frequency-domain mGIFT: the smallest
 // power of two >= N + W, W = ceil(sum_p max|i_c,p| (M-1)^p M^(3-p) / (R M^3))
 // + 1 bounds every coarse walk in bins.
+// Columns of the conjugate-pair table: fine cell f (offsets f % R - R/2 and
+// f / R - R/2, or f - R/2 for P = 1) and the cell with the negated offsets,
+// once per pair, the smaller index first; cells whose negated offsets leave
+// the lattice (an offset of -R/2 for even R) and the centre stand alone.
+void sym_columns(int R, int P, int C, std::vector<int32_t> &plus,
+                 std::vector<int32_t> &minus) {
+  const int h = R / 2;
+  for (int f = 0; f < C; ++f) {
+    const int o1 = (P >= 2 ? f % R : f) - h, o2 = P >= 2 ? f / R - h : 0;
+    const int n1 = h - o1, n2 = h - o2;
+    int g = -1;
+    if (n1 >= 0 && n1 < R && (P < 2 || (n2 >= 0 && n2 < R))) g = P >= 2 ? n1 + R * n2 : n1;
+    if (g >= 0 && g < f) continue;  // listed with g
+    plus.push_back(f);
+    minus.push_back(g > f ? g : -1);
+  }
+}
+
 int fd_pad_length(dsgrft_plan p) {
   const __int128 M = p->M;
   __int128 tot = 0;
@@ -375,6 +395,10 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
   size_t tot = 0;
   // the GEMM-form fine tables are not built for DS-KT-MFP (FFT form only)
   const size_t f16b = p->kt ? 0 : (size_t)4 * p->Cp * p->Mp * 2;
+  std::vector<int32_t> sym_plus, sym_minus;
+  if (!p->kt) sym_columns(p->R, p->P, p->C, sym_plus, sym_minus);
+  p->FBs = (int)((sym_plus.size() + 63) / 64 * 2);
+  const size_t sym_cols_n = (size_t)p->FBs * 32;
   p->det_ws_bytes = detect_ws_bytes(p->n_coarse * (int64_t)p->rows);
   const int64_t noise_parts = ((int64_t)M * N + 65535) / 65536;
   p->adj_ws_bytes = (size_t)(noise_parts + 64) * sizeof(double);
@@ -382,6 +406,8 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
       dalloc(&p->F16, f16b, tot) != hipSuccess ||
       dalloc(&p->FBF16, f16b, tot) != hipSuccess ||
       dalloc(&p->F8, f16b ? (size_t)4 * p->Cp * p->Mp : 0, tot) != hipSuccess ||
+      dalloc(&p->FS16, (size_t)2 * p->FBs * p->KB * 64 * sizeof(uint4), tot) != hipSuccess ||
+      dalloc(&p->sym_cols, 2 * sym_cols_n * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->gscbuf[0], 2 * (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
       (fft_form_supported(M) &&
        dalloc(&p->fft_tw, fft_table_elems(M, p->R, P) * sizeof(float2), tot) != hipSuccess) ||
@@ -418,7 +444,20 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
     return DSGRFT_E_DEVICE;
   }
   if (p->fft_tw) p->fft_chirp = p->fft_tw + M;
+  if (p->FBs > 0) {
+    std::vector<int32_t> cols(2 * sym_cols_n, -1);
+    for (size_t c = 0; c < sym_plus.size(); ++c) {
+      cols[c] = sym_plus[c];
+      cols[sym_cols_n + c] = sym_minus[c];
+    }
+    if (hipMemcpy(p->sym_cols, cols.data(), cols.size() * sizeof(int32_t),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      release(p);
+      return DSGRFT_E_DEVICE;
+    }
+  }
   if ((!p->kt && launch_fine_tables(p, nullptr) != hipSuccess) ||
+      (p->FBs > 0 && launch_sym_table(p, nullptr) != hipSuccess) ||
       (p->fft_tw && launch_fft_tables(p, nullptr) != hipSuccess) ||
       (p->fd && launch_fd_twiddles(p, nullptr) != hipSuccess) ||
       (p->kt && launch_kt_tables(p, nullptr) != hipSuccess) ||

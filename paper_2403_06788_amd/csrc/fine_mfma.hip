@@ -13,7 +13,8 @@
 // 4: + Fl Gl.
 //
 // k_fine_mfma3 (below) forms the fp16 split-1 product from three real
-// products per complex product instead of four.
+// products per complex product instead of four; k_fine_mfma_sym takes the
+// fine cells in conjugate pairs, four real products for two cells.
 //
 // Operand formats: fp16 and bf16 (v_mfma_f32_32x32x16, 16 pulses per K
 // step, 1 KiB fragments) and OCP e4m3 (v_mfma_scale_f32_32x32x64_f8f6f4, 64
@@ -603,6 +604,152 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
   }
 }
 
+// The fp16 search over conjugate pairs of fine cells.  A fine cell's offsets
+// d from the coarse centre are symmetric about it (R/2 on either side, for
+// even R one more on the negative side) and its phase is linear in d, so the
+// cell at -d has the conjugate fine phasor of the cell at +d.  With the four
+// real products of the +d column, Prr = Fr Gr, Pii = Fi Gi, Pri = Fr Gi,
+// Pir = Fi Gr:
+//   Y(+d) = (Prr - Pii) + j (Pri + Pir),
+//   Y(-d) = (Prr + Pii) + j (Pri - Pir),
+// the same operands, products and FP32 sums as the four-product form, but
+// half the columns: 8 MFMAs per K step and wave cover 64 cells x 64 rows
+// (12 in k_fine_mfma3, 16 in k_fine_mfma<f16, 1>).  The table F holds one
+// column per pair, plus the cells without a partner (an offset of -R/2 for
+// even R, and the centre), ordered by cols[c] (the +d cell) and
+// cols[ncols + c] (the -d cell, -1 if none); padding columns are zero.
+//
+// Tile: 64 columns x 128 rows per workgroup, 32 columns x 64 rows per wave (1
+// x 2 blocks of 32x32x16), four accumulator sets (128 registers); 12 KiB
+// stages in a ring of four LDS slots filled by LDS-DMA a pair of K steps
+// ahead, one barrier per pair, as in k_fine_mfma3.
+__global__ __launch_bounds__(256, 2) void k_fine_mfma_sym(
+    const uint4 *__restrict__ F, const uint4 *__restrict__ G,
+    const int32_t *__restrict__ cols, unsigned long long *__restrict__ packed,
+    float *__restrict__ full, int FBs, int NB, int KS, int64_t nunits, int64_t unit0,
+    int R3, int C, int rows, int GN) {
+  constexpr int NST = 4, NBG = 4, NFB = 2;     // row / column blocks per tile
+  constexpr int CH = 12 * 64, CPT = CH / 256;  // 12 fragments per stage
+  __shared__ uint4 lds[NST][CH];
+
+  const int NT = NB / NBG, FT = FBs / NFB;
+  const TileMap tm = map_tile(blockIdx.x, nunits * NT * FT, NT, FT, GN);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wf = wave & 1, wn = wave >> 1;
+  const int wbase = tid & ~63;
+
+  // Chunk c of a stage: lane c % 64, fragment c / 64: columns (re 0-1, im
+  // 2-3), then rows (re 4-7, im 8-11).
+  const uint4 *src[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int c = tid + 256 * j;
+    const int ln = c & 63, fi = c >> 6;
+    if (fi < 4) {
+      const int plane = fi >> 1, blk = fi & 1;
+      src[j] = F + (((int64_t)plane * FBs + tm.ft * NFB + blk) * KS) * 64 + ln;
+    } else {
+      const int plane = (fi - 4) >> 2, blk = (fi - 4) & 3;
+      src[j] = G + (((tm.u * 2 + plane) * NB + tm.nt * NBG + blk) * (int64_t)KS) * 64 + ln;
+    }
+  }
+  auto issue = [&](int stage) {
+    uint4 *dst = lds[stage % NST];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const unsigned la = __builtin_amdgcn_readfirstlane(
+          (unsigned)(size_t)(lds_void *)&dst[wbase + 256 * j]);
+      const uint4 *g = src[j] + (int64_t)stage * 64;
+      unsigned saved_m0;
+      asm volatile(
+          "s_mov_b32 %0, m0\n\t"
+          "s_mov_b32 m0, %1\n\t"
+          "s_nop 0\n\t"
+          "global_load_lds_dwordx4 %2, off\n\t"
+          "s_nop 0\n\t"
+          "s_mov_b32 m0, %0"
+          : "=&s"(saved_m0)
+          : "s"(la), "v"(g)
+          : "memory");
+    }
+  };
+
+  f16v acc[4][2];  // Prr, Pii, Pri, Pir per row block
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[q][j] = f16v{};
+
+  auto step = [&](int kt) {
+    const uint4 *slot = lds[kt % NST];
+    const uint4 fr = slot[wf * 64 + lane], fi = slot[(2 + wf) * 64 + lane];
+    uint4 gr[2], gi[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) gr[j] = slot[(4 + wn * 2 + j) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) gi[j] = slot[(8 + wn * 2 + j) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[0][j] = OpF16::mma({{fr}}, {{gr[j]}}, acc[0][j], 0, 0);
+      acc[1][j] = OpF16::mma({{fi}}, {{gi[j]}}, acc[1][j], 0, 0);
+      acc[2][j] = OpF16::mma({{fr}}, {{gi[j]}}, acc[2][j], 0, 0);
+      acc[3][j] = OpF16::mma({{fi}}, {{gr[j]}}, acc[3][j], 0, 0);
+    }
+  };
+
+  const int nkt = KS;
+  issue(0);
+  issue(1);
+  for (int kt = 0; kt < nkt; kt += 2) {
+    wait_copies_barrier<CPT>(0);
+    if (kt + 2 < nkt) {
+      issue(kt + 2);
+      issue(kt + 3);
+    }
+    step(kt);
+    step(kt + 1);
+  }
+
+  // ---- epilogue: both cells of each column ---------------------------------
+  const int64_t ug = unit0 + tm.u;
+  const int64_t cpos = ug / R3;
+  const unsigned fbase = (unsigned)((ug % R3) * C);
+  const int ncols = FBs * 32;
+  const int cb0 = (tm.ft * NFB + wf) * 32 + 4 * (lane >> 5);
+  int fp[16], fm[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int col = cb0 + 8 * (r >> 2) + (r & 3);
+    fp[r] = cols[col];
+    fm[r] = cols[ncols + col];
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
+    unsigned long long best = 0ull;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float prr = acc[0][j][r], pii = acc[1][j][r];
+      const float pri = acc[2][j][r], pir = acc[3][j][r];
+      const float ar = prr - pii, ai = pri + pir;  // +d
+      const float br = prr + pii, bi = pri - pir;  // -d
+      const float pa = ar * ar + ai * ai, pb = br * br + bi * bi;
+      if (fp[r] >= 0) {
+        const unsigned ff = fbase + (unsigned)fp[r];
+        best = umax64(best, ((unsigned long long)__float_as_uint(pa) << 32) | (0xffffffffu - ff));
+        if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pa;
+      }
+      if (fm[r] >= 0) {
+        const unsigned ff = fbase + (unsigned)fm[r];
+        best = umax64(best, ((unsigned long long)__float_as_uint(pb) << 32) | (0xffffffffu - ff));
+        if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pb;
+      }
+    }
+    best = umax64(best, shfl_xor64(best, 32));
+    if (lane < 32 && n < rows) atomicMax(&packed[cpos * rows + n], best);
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long *p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0ull;
@@ -671,6 +818,17 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
       hipLaunchKernelGGL(k_fine_mfma3, dim3((unsigned)tiles), dim3(256), 0, s,
                          (const uint4 *)p->F16, (const uint4 *)p->G, p->packed, full, p->FB,
                          p->NB, p->Mp / OpF16::KSTEP, nunits, unit0, p->R3, p->C, p->rows, 8);
+      return hipGetLastError();
+    }
+    case DSGRFT_FORM_F16_SYM: {
+      if (split != 1 || (p->Mp / OpF16::KSTEP) % 2 != 0 || p->FBs <= 0 || p->FBs % 2 != 0 ||
+          p->NB % 4 != 0)
+        return hipErrorInvalidValue;
+      const int64_t tiles = nunits * (p->NB / 4) * (p->FBs / 2);
+      hipLaunchKernelGGL(k_fine_mfma_sym, dim3((unsigned)tiles), dim3(256), 0, s,
+                         (const uint4 *)p->FS16, (const uint4 *)p->G, p->sym_cols, p->packed,
+                         full, p->FBs, p->NB, p->Mp / OpF16::KSTEP, nunits, unit0, p->R3, p->C,
+                         p->rows, 8);
       return hipGetLastError();
     }
     case DSGRFT_FORM_BF16:

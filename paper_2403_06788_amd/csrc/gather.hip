@@ -316,7 +316,7 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
   hipLaunchKernelGGL((k_gather_lp<T, NP>), grid, dim3(256), 0, s, src.echo, p->u_off,   \
                      p->u_psi, p->M, src.N, p->Mp, p->rows, src.n_begin,                \
                      src.unit_stride, p->NB, p->KB, nunits, G)
-  if (form == DSGRFT_FORM_F16 || form == DSGRFT_FORM_F16_3M) {
+  if (form == DSGRFT_FORM_F16 || form == DSGRFT_FORM_F16_3M || form == DSGRFT_FORM_F16_SYM) {
     if (!lo) DS_GATHER_LP(_Float16, 2); else DS_GATHER_LP(_Float16, 4);
   } else if (form == DSGRFT_FORM_BF16 || form == DSGRFT_FORM_BF16_GLO) {
     if (!lo) DS_GATHER_LP(__bf16, 2); else DS_GATHER_LP(__bf16, 4);

@@ -75,6 +75,10 @@ struct dsgrft_plan_s {
   uint4 *F16;           // MFMA fragments, 4 planes (re_hi, im_hi, re_lo, im_lo)
   uint4 *FBF16;         // same in bf16
   uint4 *F8;            // e4m3 fragments (K blocks of 64), same 4 planes
+  int FBs;              // column blocks of the conjugate-pair table (even)
+  uint4 *FS16;          // its fp16 fragments, 2 planes (re, im) x FBs blocks
+  int32_t *sym_cols;    // [2][FBs * 32]: fine cell of +d and of -d per
+                        //   column (-1: none)
   int32_t *u_off;       // [batch_units][Mp] unit range offsets
   float2 *u_psi;        // [batch_units][Mp] unit de-ramp phasors
   void *G;              // gathered batch being produced or consumed (a slot
@@ -154,6 +158,7 @@ __host__ __device__ inline void fine_offsets(int R, int P, int64_t f, int64_t fo
   } while (0)
 
 hipError_t launch_fine_tables(dsgrft_plan p, hipStream_t s);
+hipError_t launch_sym_table(dsgrft_plan p, hipStream_t s);
 hipError_t launch_unit_tables(dsgrft_plan p, const int64_t *cells,
                               int64_t cc_base, int64_t unit0, int64_t nunits,
                               hipStream_t s);

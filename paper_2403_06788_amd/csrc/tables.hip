@@ -92,6 +92,20 @@ __global__ void k_fine_tables(int M, int Mp, int C, int Cp, int R, int P, Lat L,
   }
 }
 
+// Conjugate-pair table: column c of block c / 32 holds the fp16 fragments of
+// fine cell cols[c] (zero where cols[c] < 0), copied from the F16 hi planes.
+__global__ void k_sym_table(const uint4 *__restrict__ F16, const int32_t *__restrict__ cols,
+                            int FB, int FBs, int KB, uint4 *__restrict__ FS) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)2 * FBs * KB * 64) return;
+  const int lane = (int)(t & 63);
+  const int64_t q = t >> 6;
+  const int kb = (int)(q % KB), cb = (int)((q / KB) % FBs), plane = (int)(q / ((int64_t)KB * FBs));
+  const int f = cols[cb * 32 + (lane & 31)];
+  FS[t] = f < 0 ? make_uint4(0u, 0u, 0u, 0u)
+                : F16[(((int64_t)plane * FB + (f >> 5)) * KB + kb) * 64 + (f & 31) + 32 * (lane >> 5)];
+}
+
 __global__ void k_unit_tables(const int64_t *cells, int64_t cc_base,
                               int64_t unit0, int64_t nunits, int M, int Mp,
                               int R3, int R, int P, int K0, int K1, int K2,
@@ -146,6 +160,13 @@ hipError_t launch_fine_tables(dsgrft_plan p, hipStream_t s) {
                      p->Mp, p->C, p->Cp, p->R, p->P, p->lat, p->F32,
                      (uint16_t *)p->F16, (uint16_t *)p->FBF16,
                      (uint8_t *)p->F8, p->KB, p->FB);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_table(dsgrft_plan p, hipStream_t s) {
+  const int64_t n = (int64_t)2 * p->FBs * p->KB * 64;
+  hipLaunchKernelGGL(k_sym_table, dim3(blocks(n, 256)), dim3(256), 0, s, p->F16,
+                     p->sym_cols, p->FB, p->FBs, p->KB, p->FS16);
   return hipGetLastError();
 }
 

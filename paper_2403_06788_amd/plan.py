@@ -114,8 +114,9 @@ class Plan:
 
         form/split: "f32" (vector ALUs) and "f32fft" (slow-time FFT) with
         split 1; "f16", "bf16", "fp8" with split 1-4 products; "f16_3m"
-        (three real products per complex product) with split 1; "bf16_glo"
-        (the gathered rows split) with split 2."""
+        (three real products per complex product) with split 1; "f16_sym"
+        (fine cells in conjugate pairs, four real products per pair) with
+        split 1; "bf16_glo" (the gathered rows split) with split 2."""
         echo = _echo(echo)
         if cells is not None:
             cells = cells.to(device="cuda", dtype=torch.int64).contiguous()

@@ -11,7 +11,7 @@ from oracle.grid import Axis, Radar, make_grid
 
 pytestmark = pytest.mark.gpu
 
-FORMS = [("f32", 1, 1e-5), ("f16", 1, 1e-3), ("f16_3m", 1, 1e-3), ("bf16", 3, 1e-4),
+FORMS = [("f32", 1, 1e-5), ("f16", 1, 1e-3), ("f16_3m", 1, 1e-3), ("f16_sym", 1, 1e-3), ("bf16", 3, 1e-4),
          ("fp8", 3, 1e-2), ("bf16_glo", 2, 1e-2)]
 
 # (fc, fs, prf, M, N, order, axes): one pulse and one bin; two pulses; a
@@ -78,8 +78,9 @@ def test_single_impulse_every_form():
     # (Gr + Gi)(Fr + Fi)(d1 + d2) from rounding the two sums, at most 4u|Y|
     # more, so |dY| <= 6u|Y| and |dP| <= 12u P.  bf16 x3 ~ u^2; bf16 with
     # the rows split keeps the table's rounding only (2u, u = 2^-8); e4m3 x3
-    # leaves out Fl Gl and keeps ~2^-8 per operand.
-    bound = {"f32": 1e-6, "f16": 4 * 2.0 ** -11, "f16_3m": 12 * 2.0 ** -11,
+    # leaves out Fl Gl and keeps ~2^-8 per operand.  The conjugate-pair form
+    # takes the four-product form's operands and products (4u).
+    bound = {"f32": 1e-6, "f16": 4 * 2.0 ** -11, "f16_3m": 12 * 2.0 ** -11, "f16_sym": 4 * 2.0 ** -11,
              "bf16_glo": 4 * 2.0 ** -8,
              "bf16": 1e-4, "fp8": 8 * 2.0 ** -8}
     for form, split, _ in FORMS:

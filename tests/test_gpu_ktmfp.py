@@ -225,7 +225,7 @@ def test_kt_rejects_what_it_does_not_support():
         Plan(c["fc"], c["fs"], c["prf"], 96, 128, 2, c["axes"], mgift="kt")
     p = _plan(c)
     e = torch.zeros((64, 128), dtype=torch.complex64, device="cuda")
-    for form in ("f32", "f16", "bf16", "fp8", "f16_3m"):
+    for form in ("f32", "f16", "bf16", "fp8", "f16_3m", "f16_sym"):
         with pytest.raises(DsgrftError, match="unsupported"):
             p.search(e, form, 1)
     with pytest.raises(DsgrftError, match="invalid"):

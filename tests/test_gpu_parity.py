@@ -16,7 +16,8 @@ pytestmark = pytest.mark.gpu
 
 TOL = {("f32", 1): 1e-5, ("f16", 1): 1e-3, ("f16", 2): 1e-3, ("f16", 3): 1e-5,
        ("f16", 4): 1e-5, ("bf16", 1): 1e-2, ("bf16", 2): 1e-2, ("bf16", 3): 1e-4,
-       ("bf16", 4): 1e-4, ("f16_3m", 1): 1e-3, ("bf16_glo", 2): 1e-2}
+       ("bf16", 4): 1e-4, ("f16_3m", 1): 1e-3, ("bf16_glo", 2): 1e-2,
+       ("f16_sym", 1): 1e-3}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -137,6 +138,8 @@ def test_three_product_form_takes_split_one_only(case):
     from paper_2403_06788_amd._lib import DsgrftError
     with pytest.raises(DsgrftError, match="invalid"):
         case["plan"].search(case["echo_dev"], "f16_3m", 2)
+    with pytest.raises(DsgrftError, match="invalid"):
+        case["plan"].search(case["echo_dev"], "f16_sym", 2)
     for split in (1, 3):
         with pytest.raises(DsgrftError, match="invalid"):
             case["plan"].search(case["echo_dev"], "bf16_glo", split)
