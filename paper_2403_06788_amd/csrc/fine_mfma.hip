@@ -620,10 +620,11 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
 // cols[ncols + c] (the -d cell, -1 if none); padding columns are zero.
 //
 // Tile: 64 columns x 128 rows per workgroup, 32 columns x 64 rows per wave (1
-// x 2 blocks of 32x32x16), four accumulator sets (128 registers); 12 KiB
-// stages in a ring of four LDS slots filled by LDS-DMA a pair of K steps
-// ahead, one barrier per pair, as in k_fine_mfma3.
-__global__ __launch_bounds__(256, 2) void k_fine_mfma_sym(
+// x 2 blocks of 32x32x16), four accumulator sets (128 registers, 167 in
+// all); 12 KiB stages in a ring of four LDS slots filled by LDS-DMA a pair of
+// K steps ahead, one barrier per pair, as in k_fine_mfma3.  Three workgroups
+// share a CU (144 KiB of LDS, three waves per SIMD).
+__global__ __launch_bounds__(256, 3) void k_fine_mfma_sym(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
     const int32_t *__restrict__ cols, unsigned long long *__restrict__ packed,
     float *__restrict__ full, int FBs, int NB, int KS, int64_t nunits, int64_t unit0,
@@ -716,37 +717,36 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma_sym(
   const unsigned fbase = (unsigned)((ug % R3) * C);
   const int ncols = FBs * 32;
   const int cb0 = (tm.ft * NFB + wf) * 32 + 4 * (lane >> 5);
-  int fp[16], fm[16];
+  unsigned long long best[2] = {0ull, 0ull};
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int col = cb0 + 8 * (r >> 2) + (r & 3);
-    fp[r] = cols[col];
-    fm[r] = cols[ncols + col];
-  }
+    const int fp = cols[col], fm = cols[ncols + col];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
-    unsigned long long best = 0ull;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int j = 0; j < 2; ++j) {
+      const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
       const float prr = acc[0][j][r], pii = acc[1][j][r];
       const float pri = acc[2][j][r], pir = acc[3][j][r];
       const float ar = prr - pii, ai = pri + pir;  // +d
       const float br = prr + pii, bi = pri - pir;  // -d
       const float pa = ar * ar + ai * ai, pb = br * br + bi * bi;
-      if (fp[r] >= 0) {
-        const unsigned ff = fbase + (unsigned)fp[r];
-        best = umax64(best, ((unsigned long long)__float_as_uint(pa) << 32) | (0xffffffffu - ff));
+      if (fp >= 0) {
+        const unsigned ff = fbase + (unsigned)fp;
+        best[j] = umax64(best[j], ((unsigned long long)__float_as_uint(pa) << 32) | (0xffffffffu - ff));
         if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pa;
       }
-      if (fm[r] >= 0) {
-        const unsigned ff = fbase + (unsigned)fm[r];
-        best = umax64(best, ((unsigned long long)__float_as_uint(pb) << 32) | (0xffffffffu - ff));
+      if (fm >= 0) {
+        const unsigned ff = fbase + (unsigned)fm;
+        best[j] = umax64(best[j], ((unsigned long long)__float_as_uint(pb) << 32) | (0xffffffffu - ff));
         if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pb;
       }
     }
-    best = umax64(best, shfl_xor64(best, 32));
-    if (lane < 32 && n < rows) atomicMax(&packed[cpos * rows + n], best);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
+    const unsigned long long b = umax64(best[j], shfl_xor64(best[j], 32));
+    if (lane < 32 && n < rows) atomicMax(&packed[cpos * rows + n], b);
   }
 }
 
