@@ -22,6 +22,11 @@ CASES = {
     "p2rows": dict(fc=1.2e8, fs=1.0e7, prf=500.0, M=100, N=300, order=2,
                    axes=[(-100.0, 100.0), (-400.0, 400.0)], targets=3,
                    snr_db=-3.0, rows=(37, 261)),
+    # P = 2 with an odd R = 13: every fine cell but the centre has its
+    # conjugate partner (169 cells in 85 pair columns)
+    "p2odd": dict(fc=1.3e8, fs=1.0e7, prf=500.0, M=64, N=160, order=2,
+                  axes=[(-200.0, 200.0), (-300.0, 300.0)], targets=2, snr_db=-3.0,
+                  rows=None),
     # P = 3, R = 6 (36 columns x 6 jerk units per coarse cell), M = 72
     "p3": dict(fc=6.0e7, fs=1.0e7, prf=500.0, M=72, N=200, order=3,
                axes=[(-150.0, 150.0), (-600.0, 600.0), (-9000.0, 9000.0)],
