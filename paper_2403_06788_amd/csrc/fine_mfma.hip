@@ -623,7 +623,8 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
 // x 2 blocks of 32x32x16), four accumulator sets (128 registers, 167 in
 // all); 12 KiB stages in a ring of four LDS slots filled by LDS-DMA a pair of
 // K steps ahead, one barrier per pair, as in k_fine_mfma3.  Three workgroups
-// share a CU (144 KiB of LDS, three waves per SIMD).
+// share a CU (144 KiB of LDS, three waves per SIMD).  Tiles are grouped by
+// four row tiles (GN = 4; 8 and 16 were 3% and 9% slower, 2 and 6 within 1%).
 __global__ __launch_bounds__(256, 3) void k_fine_mfma_sym(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
     const int32_t *__restrict__ cols, unsigned long long *__restrict__ packed,
@@ -828,7 +829,7 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
       hipLaunchKernelGGL(k_fine_mfma_sym, dim3((unsigned)tiles), dim3(256), 0, s,
                          (const uint4 *)p->FS16, (const uint4 *)p->G, p->sym_cols, p->packed,
                          full, p->FBs, p->NB, p->Mp / OpF16::KSTEP, nunits, unit0, p->R3, p->C,
-                         p->rows, 8);
+                         p->rows, 4);
       return hipGetLastError();
     }
     case DSGRFT_FORM_BF16:
