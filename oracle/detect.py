@@ -36,8 +36,10 @@ def reduce_power(power: np.ndarray):
     return power.max(axis=-1), power.argmax(axis=-1).astype(np.int32)
 
 
-def dsgrft_reduced(echo, grid: Grid, cells=None, rows=None, chunk=1024):
-    """Reduced DS-GRFT map for the listed coarse cells.
+def dsgrft_reduced(echo, grid: Grid, cells=None, rows=None, chunk=1024, H=None):
+    """Reduced DS-GRFT map for the listed coarse cells, rows taken `chunk` at
+    a time.  H: the fine matrix (transforms.fine_matrix(grid)) if the caller
+    has it, else it is rebuilt for every chunk.
 
     Returns (pmax [n_cells, rows] float64, argf [n_cells, rows] int32).
     """
@@ -48,7 +50,7 @@ def dsgrft_reduced(echo, grid: Grid, cells=None, rows=None, chunk=1024):
     af = np.empty((len(cells), len(r_all)), dtype=np.int32)
     for ci, k in enumerate(cells):
         for s in range(0, len(r_all), chunk):
-            y = dsgrft_cell(echo, grid, k, rows=r_all[s:s + chunk])
+            y = dsgrft_cell(echo, grid, k, rows=r_all[s:s + chunk], H=H)
             p, a = reduce_power(np.abs(y) ** 2)
             pm[ci, s:s + chunk] = p
             af[ci, s:s + chunk] = a

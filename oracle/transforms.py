@@ -70,14 +70,17 @@ def mgift(echo: np.ndarray, grid: Grid, k: int, rows=None) -> np.ndarray:
     return y * h_pre[:, None]
 
 
-def gft(y_c: np.ndarray, grid: Grid, fine=None) -> np.ndarray:
-    """Alg. 2 / eq. (44): sum_m y_c[m, n] * H_fine[m, f] -> [rows, F]."""
-    return y_c.T @ fine_matrix(grid, fine)
+def gft(y_c: np.ndarray, grid: Grid, fine=None, H=None) -> np.ndarray:
+    """Alg. 2 / eq. (44): sum_m y_c[m, n] * H_fine[m, f] -> [rows, F].
+
+    H, if given, is fine_matrix(grid, fine) computed once by the caller (the
+    table does not depend on the cell, so a loop over cells may reuse it)."""
+    return y_c.T @ (fine_matrix(grid, fine) if H is None else H)
 
 
-def dsgrft_cell(echo, grid: Grid, k: int, rows=None, fine=None) -> np.ndarray:
+def dsgrft_cell(echo, grid: Grid, k: int, rows=None, fine=None, H=None) -> np.ndarray:
     """Complex DS-GRFT outputs of coarse cell k: [rows, F] complex128."""
-    return gft(mgift(echo, grid, k, rows), grid, fine)
+    return gft(mgift(echo, grid, k, rows), grid, fine, H)
 
 
 # ---- TD-GRFT (single scale) ----------------------------------------------

@@ -84,3 +84,38 @@ def test_sinc_derivative_series_branch_is_continuous():
     h = 1e-6
     fd = (np.sinc(0.37 + h) - np.sinc(0.37 - h)) / (2 * h)
     assert d[5] == pytest.approx(fd, rel=1e-8)
+
+
+def test_batch_weighted_echo_gradient_two_candidates():
+    """batch(): J and dJ/dtheta per candidate equal objective()/gradients(),
+    and the echo gradient is the grad_J-weighted sum over candidates, checked
+    against central differences of L(s) = sum_b grad_J[b] J_b(s) in the real
+    and imaginary part of each sampled echo entry (a dropped or misapplied
+    weight changes L's gradient)."""
+    g, echo = grid_and_echo(M=12, N=20, seed=6)
+    thetas = np.array([[9.3 * g.dr, 7.0, -3.0], [4.6 * g.dr, -11.0, 5.5]])
+    gJ = np.array([0.7, -1.9])
+    J, G, ge = A.batch(echo, g, thetas, grad_J=gJ, want_echo_grad=True)
+    for b in range(2):
+        jb, _, gb, _ = A.gradients(echo, g, thetas[b])
+        assert J[b] == jb and np.array_equal(G[b], gb)
+        assert J[b] == pytest.approx(A.objective(echo, g, thetas[b])[0], rel=1e-13)
+
+    def L(s):
+        return sum(gJ[b] * A.objective(s, g, thetas[b])[0] for b in range(2))
+
+    rng = np.random.default_rng(8)
+    h = 1e-6
+    for _ in range(12):
+        m, n = int(rng.integers(12)), int(rng.integers(20))
+        d = np.zeros_like(echo)
+        d[m, n] = h
+        fre = (L(echo + d) - L(echo - d)) / (2 * h)
+        fim = (L(echo + 1j * d) - L(echo - 1j * d)) / (2 * h)
+        assert ge[m, n].real == pytest.approx(fre, rel=1e-6, abs=1e-8)
+        assert ge[m, n].imag == pytest.approx(fim, rel=1e-6, abs=1e-8)
+    # unit weights when grad_J is omitted; no echo gradient unless asked
+    _, _, ge1 = A.batch(echo, g, thetas, want_echo_grad=True)
+    ref = A.gradients(echo, g, thetas[0])[3] + A.gradients(echo, g, thetas[1])[3]
+    assert np.abs(ge1 - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert A.batch(echo, g, thetas)[2] is None

@@ -123,3 +123,51 @@ def test_walk_bound_covers_every_walk():
         assert worst <= W
         Np = fd.pad_length(g)
         assert Np >= g.N + W and Np & (Np - 1) == 0 and Np < 2 * (g.N + W)
+
+
+def test_fd_power_direct_sums_tiny():
+    """dsgrft_fd_power on every cell, row and fine cell of a tiny plan against
+    the defining sums written out term by term: the frequency-domain shift
+    of each pulse (range DFT, ramp, inverse DFT, all as plain sums with the
+    walk as an exact fraction) times the whole phase of the lattice point,
+    exp(+j 2 pi (i1 m M^2 + i2 m^2 M) / M^3) with i = centre + fine offset
+    (no coarse/fine factorisation), summed over pulses.  A transposed
+    operand, a conjugated fine table or a wrong fine ordering fails it."""
+    r = Radar(3.0e7, 1.0e7, 100.0)            # R = 3, offsets -1, 0, 1
+    M, N = 3, 5
+    g = make_grid(r, M, N, 2, [Axis(-40.0, 40.0), Axis(-200.0, 200.0)])
+    rng = np.random.default_rng(11)
+    e = rng.standard_normal((M, N)) + 1j * rng.standard_normal((M, N))
+    Np = fd.pad_length(g)
+    P = fd.dsgrft_fd_power(e, g)
+    assert P.shape == (g.n_coarse, N, g.R ** 2)
+    M3 = M ** 3
+    for k in range(g.n_coarse):
+        ic = g.centre(k)
+        for n in range(N):
+            for f in range(g.R ** 2):
+                i1 = ic[0] + f % g.R - g.h
+                i2 = ic[1] + f // g.R - g.h
+                Y = 0j
+                for m in range(M):
+                    x = Fraction(ic[0] * m * M * M + ic[1] * m * m * M, g.R * M3)
+                    acc = 0j
+                    for kk in range(Np):
+                        ks = kk if kk < Np // 2 else kk - Np
+                        Sk = sum(e[m, q] * np.exp(-2j * np.pi * kk * q / Np) for q in range(N))
+                        ph = float((ks * x) % Np) / Np
+                        acc += Sk * np.exp(2j * np.pi * ph) * np.exp(2j * np.pi * kk * n / Np)
+                    turn = Fraction((i1 * m * M * M + i2 * m * m * M) % M3, M3)
+                    Y += acc / Np * np.exp(2j * np.pi * float(turn))
+                assert abs(abs(Y) ** 2 - P[k, n, f]) <= 1e-10 * max(1.0, abs(Y) ** 2)
+
+
+def test_fd_power_equals_time_domain_map_on_integer_walk():
+    """On the integer-walk cell the frequency-domain map is the time-domain
+    DS-GRFT map (transforms.dsgrft_power); on the fractional cell it is not."""
+    g = _int_walk_grid()
+    e = np.random.default_rng(12).standard_normal((8, 40)) * (0.3 - 1.1j)
+    P_fd = fd.dsgrft_fd_power(e, g, cells=[0, 1])
+    P_td = OT.dsgrft_power(e, g, cells=[0, 1])
+    assert np.abs(P_fd[0] - P_td[0]).max() <= 1e-11 * P_td[0].max()
+    assert np.abs(P_fd[1] - P_td[1]).max() > 1e-2 * P_td[1].max()
