@@ -23,16 +23,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "DS-GRFT cells·pulses/s (M=1024); MFMA vs FP32 speedup at rel err≤1e-3"
-PEAK_TFLOPS = {"f16": 2500.0, "f16_3m": 2500.0, "f16_sym": 2500.0, "bf16": 2500.0, "fp8": 5000.0, "f32": 157.3,
+PEAK_TFLOPS = {"f16": 2500.0, "f16_3m": 2500.0, "f16_sym": 2500.0, "bf16": 2500.0,
+               "bf16_glo": 2500.0, "bf16_sym": 2500.0, "fp8": 5000.0, "f32": 157.3,
                "f32fft": 157.3}
-DTYPE = {"f16_3m": "f16", "f16_sym": "f16", "f32fft": "f32"}
+DTYPE = {"f16_3m": "f16", "f16_sym": "f16", "f32fft": "f32", "bf16_glo": "bf16",
+         "bf16_sym": "bf16"}
 KERNEL = {"f16_3m": "k_fine_mfma3 (f16, three real products per complex product)",
-          "f16_sym": "k_fine_mfma_sym (f16, fine cells in conjugate pairs, four real products per pair)"}
+          "f16_sym": "k_fine_mfma_sym<f16> (f16, fine cells in conjugate pairs, four real "
+                     "products per pair)",
+          "bf16_sym": "k_fine_mfma_sym<bf16> (bf16 split parts over conjugate pairs of fine "
+                      "cells, four real products per pair and part)"}
 FORM_TEXT = {"f16_3m": "f16 MFMA, three real products per complex product (Gauss), split 1, "
                        "FP32 accumulation",
              "f16_sym": "f16 MFMA, fine cells in conjugate pairs (four real products for the "
                         "cells at +d and -d), split 1, FP32 accumulation",
+             "bf16_sym": "bf16 MFMA over conjugate pairs of fine cells, split parts Fh Gh + Fh Gl "
+                         "(+ Fl Gh for split 3), FP32 accumulation",
              "f32fft": "FP32, fine velocities by slow-time FFT"}
+SWEEP = (("f16_sym", 1), ("f16_3m", 1), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4),
+         ("bf16_sym", 2), ("bf16_sym", 3), ("bf16", 1), ("bf16", 2), ("bf16_glo", 2),
+         ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3), ("fp8", 4),
+         ("f32fft", 1))
+SWEEP_STEPS = 3
 HBM_GBPS = 8000.0
 FINE_SRC = os.path.join(ROOT, "paper_2403_06788_amd", "csrc", "fine_mfma.hip")
 
@@ -90,6 +102,43 @@ def oracle_rows(echo, grid, cells, rows, mgift="td"):
     return out
 
 
+def fine_roofline(plan, prof, form, split):
+    """Roofline of the fine-search kernel from a dsgrft_profile: the
+    algorithmic rate (8 flops per cell-pulse; for the FFT form the radix-2
+    FFT flops of its transforms) and, for the MFMA forms, the executed MFMA
+    rate (launched matrix products, padding included)."""
+    launches = max(prof["fine_launches"], 1)
+    avg_s = prof["fine_ms"] / launches * 1e-3
+    fft = form == "f32fft"
+    if fft:
+        # FFT form: R de-chirped M-point FFTs per (unit, row), not 8 flops
+        # per cell-pulse
+        flops = prof["fine_cell_pulses"] / launches / (plan.M * plan.R * plan.R) \
+            * plan.R * fft_flops(plan.M)
+    else:
+        flops = prof["fine_flops"] / launches
+    peak = PEAK_TFLOPS[form]
+    achieved = flops / avg_s / 1e12
+    out = {"bound": "alu" if fft else "mfma", "achieved": round(achieved, 2),
+           "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+           "traffic": None if fft else recorded_traffic(form, split),
+           "mfma_util": None if fft else recorded_mfma_util(form, split),
+           "kernel": f"k_fine_fft_w<{plan.M // 64}>" if fft
+                     else KERNEL.get(form, f"k_fine_mfma<{form}, split {split}>"),
+           "avg_launch_ms": round(avg_s * 1e3, 4),
+           "flops_per_launch": flops,
+           "launches": prof["fine_launches"]}
+    if form not in ("f32", "f32fft"):
+        ex = prof["fine_mfma_flops"] / launches
+        out["executed"] = {"tflops": round(ex / avg_s / 1e12, 2),
+                           "frac": round(ex / avg_s / 1e12 / peak, 4),
+                           "flops_per_launch": ex,
+                           "note": "launched MFMA products (padding included) over the "
+                                   "same launch time; achieved/frac above count 8 flops per "
+                                   "cell-pulse"}
+    return out
+
+
 def sampled_error(pm, af, ref, rows, tol):
     """max |dP|/P_ref_max over sampled rows, and argmax agreement (near-tie
     rule: exact where the oracle's top-2 gap exceeds 2 tol * scale)."""
@@ -120,7 +169,8 @@ def main():
     ap.add_argument("--mgift", default="td", choices=("td", "fd"),
                     help="coarse compensation: time-domain gather or frequency domain")
     ap.add_argument("--split", type=int, default=1)
-    ap.add_argument("--f32-cells", type=int, default=48)
+    ap.add_argument("--f32-cells", type=int, default=96)
+    ap.add_argument("--f32-repeats", type=int, default=3)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-pass", action="store_true",
@@ -166,13 +216,13 @@ def main():
     echo = torch.from_numpy(echo_np).cuda()
     cells = plan.n_coarse
     cp_total = float(cells) * plan.rows * plan.n_fine * plan.M
-    gamma2 = plan.threshold(1.0, 1e-9)   # sigma^2 = 1 (synthetic), P_FA = 1e-9
+    pfa = 1e-9                           # LRT at sigma^2 = 1 (synthetic noise power)
     pm = torch.empty((cells, plan.rows), dtype=torch.float32, device="cuda")
     af = torch.empty((cells, plan.rows), dtype=torch.int32, device="cuda")
 
     def step(form, split, n=cells):
         plan.search(echo, form, split, n=n, out=(pm[:n], af[:n]))
-        return plan.detect(pm[:n], af[:n], gamma2, cap=4096) if n == cells else None
+        return plan.detect(pm[:n], af[:n], pfa, 1.0, cap=4096) if n == cells else None
 
     if args.profile_pass:
         # calibration copy of known size, then one search of 16 cells
@@ -203,7 +253,7 @@ def main():
     value = cp_total / (ms * 1e-3)
     log(f"timed {args.steps} steps: {ms:.1f} ms/step, {value:.3e} cells*pulses/s")
     pm_main, af_main = pm.cpu().numpy(), af.cpu().numpy()
-    peaks, count, best = plan.detect(pm, af, gamma2, cap=4096)
+    peaks, count, best = plan.detect(pm, af, pfa, 1.0, cap=4096)
     # cell-averaging CFAR along range on the same reduced map (beside the LRT)
     plan.detect_cfar(pm, af, 2, 16, 1.5, cap=4096)
     torch.cuda.synchronize()
@@ -211,28 +261,11 @@ def main():
     _, cfar_count, _ = plan.detect_cfar(pm, af, 2, 16, 1.5, cap=4096)
     cfar_ms = (time.perf_counter() - t) * 1e3
 
-    fine_avg_s = prof["fine_ms"] / max(prof["fine_launches"], 1) * 1e-3
-    fft = args.form == "f32fft"
-    if fft:
-        # FFT form: R de-chirped M-point FFTs per (unit, row), not 8 flops
-        # per cell-pulse
-        fine_flops_launch = prof["fine_cell_pulses"] / max(prof["fine_launches"], 1) \
-            / (plan.M * plan.R * plan.R) * plan.R * fft_flops(plan.M)
-    else:
-        fine_flops_launch = prof["fine_flops"] / max(prof["fine_launches"], 1)
-    achieved = fine_flops_launch / fine_avg_s / 1e12
-    peak = PEAK_TFLOPS[args.form]
+    roofline = fine_roofline(plan, prof, args.form, args.split)
+    fine_avg_s = roofline["avg_launch_ms"] * 1e-3
+    achieved, peak = roofline["achieved"], roofline["peak"]
     gather_avg_s = prof["gather_ms"] / max(prof["gather_launches"], 1) * 1e-3
     gather_bytes = prof["gather_bytes"] / max(prof["gather_launches"], 1)
-    roofline = {"bound": "alu" if fft else "mfma", "achieved": round(achieved, 2),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": None if fft else recorded_traffic(args.form, args.split),
-                "mfma_util": None if fft else recorded_mfma_util(args.form, args.split),
-                "kernel": f"k_fine_fft_w<{plan.M // 64}>" if fft
-                          else KERNEL.get(args.form, f"k_fine_mfma<{args.form}, split {args.split}>"),
-                "avg_launch_ms": round(fine_avg_s * 1e3, 4),
-                "flops_per_launch": fine_flops_launch,
-                "launches": prof["fine_launches"]}
     gather = {"bound": "hbm", "achieved": round(gather_bytes / gather_avg_s / 1e9, 1),
               "peak": HBM_GBPS, "unit": "GB/s",
               "frac": round(gather_bytes / gather_avg_s / 1e9 / HBM_GBPS, 4),
@@ -274,46 +307,59 @@ def main():
     forms = {}
     err, bad, clear, scale = sampled_error(pm_main, af_main, ref, s_rows, 1e-3)
     forms[f"{args.form}x{args.split}"] = {"cells_pulses_per_s": value, "ms": round(ms, 2),
-                                         "rel_err": err, "argmax_bad": bad,
-                                         "argmax_checked": clear}
-    # ---- other forms: one warm step each ----------------------------------
+                                         "steps": args.steps, "rel_err": err,
+                                         "argmax_bad": bad, "argmax_checked": clear,
+                                         "roofline_frac": roofline["frac"],
+                                         "executed_frac": roofline.get("executed", {}).get("frac"),
+                                         "mfma_util": roofline["mfma_util"],
+                                         "fine_avg_launch_ms": roofline["avg_launch_ms"]}
+    # ---- other forms: a 16-cell warm-up, then SWEEP_STEPS timed steps -------
     if not args.no_sweep:
-        for form, split in (("f16_sym", 1), ("f16_3m", 1), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4),
-                            ("bf16", 1), ("bf16", 2), ("bf16_glo", 2),
-                            ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3),
-                            ("fp8", 4), ("f32fft", 1)):
+        for form, split in SWEEP:
             if (form, split) == (args.form, args.split):
                 continue
             step(form, split, n=16)
             torch.cuda.synchronize()
+            plan.profile_begin(4096)
             t = time.perf_counter()
-            step(form, split)
+            for _ in range(SWEEP_STEPS):
+                step(form, split)
             torch.cuda.synchronize()
-            dt = time.perf_counter() - t
+            dt = (time.perf_counter() - t) / SWEEP_STEPS
+            rf = fine_roofline(plan, plan.profile_end(), form, split)
             e, b, cl, _ = sampled_error(pm.cpu().numpy(), af.cpu().numpy(), ref, s_rows, 1e-3)
             forms[f"{form}x{split}"] = {"cells_pulses_per_s": cp_total / dt,
-                                        "ms": round(dt * 1e3, 2), "rel_err": e,
-                                        "argmax_bad": b, "argmax_checked": cl}
-            log(f"{form}x{split}: {dt * 1e3:.1f} ms, rel err {e:.2e}")
+                                        "ms": round(dt * 1e3, 2), "steps": SWEEP_STEPS,
+                                        "rel_err": e, "argmax_bad": b, "argmax_checked": cl,
+                                        "roofline_frac": rf["frac"],
+                                        "executed_frac": rf.get("executed", {}).get("frac"),
+                                        "mfma_util": rf["mfma_util"],
+                                        "fine_avg_launch_ms": rf["avg_launch_ms"]}
+            log(f"{form}x{split}: {dt * 1e3:.1f} ms, rel err {e:.2e}, "
+                f"{rf['frac']:.3f} of peak (algorithmic)")
     # ---- plain FP32 form on a sample of coarse cells ------------------------
     n32 = min(args.f32_cells, cells)
     step("f32", 1, n=16)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    step("f32", 1, n=n32)
+    for _ in range(args.f32_repeats):
+        step("f32", 1, n=n32)
     torch.cuda.synchronize()
-    dt32 = time.perf_counter() - t
+    dt32 = (time.perf_counter() - t) / args.f32_repeats
     cp32 = float(n32) * plan.rows * plan.n_fine * plan.M
     f32_rate = cp32 / dt32
     pm32, af32 = pm[:n32].cpu().numpy(), af[:n32].cpu().numpy()
     ref32 = {k: v for k, v in ref.items() if k < n32}
     e32 = sampled_error(pm32, af32, ref32, s_rows, 1e-5)[0] if ref32 else None
     forms["f32x1"] = {"cells_pulses_per_s": f32_rate, "sample_cells": n32,
-                      "ms_sample": round(dt32 * 1e3, 2), "rel_err": e32}
-    log(f"f32 plain: {f32_rate:.3e} cells*pulses/s on {n32} cells")
+                      "repeats": args.f32_repeats, "ms_sample": round(dt32 * 1e3, 2),
+                      "rel_err": e32}
+    log(f"f32 plain: {f32_rate:.3e} cells*pulses/s on {n32} cells x {args.f32_repeats}")
     ok_forms = {k: v for k, v in forms.items()
                 if k != "f32x1" and v["rel_err"] <= 1e-3 and v["argmax_bad"] == 0}
     fastest = max(ok_forms, key=lambda k: ok_forms[k]["cells_pulses_per_s"]) if ok_forms else None
+    bf16_ok = [k for k in ok_forms if k.startswith("bf16")]
+    bf16_best = max(bf16_ok, key=lambda k: ok_forms[k]["cells_pulses_per_s"]) if bf16_ok else None
 
     # ---- CPU baseline: the oracle on a bounded sample ------------------------
     cpu = None
@@ -365,6 +411,12 @@ def main():
         "fastest_within_1e-3": None if fastest is None else {
             "form": fastest, "cells_pulses_per_s": ok_forms[fastest]["cells_pulses_per_s"],
             "speedup_vs_f32": round(ok_forms[fastest]["cells_pulses_per_s"] / f32_rate, 2)},
+        "bf16_fastest_within_1e-3": None if bf16_best is None else {
+            "form": bf16_best, "cells_pulses_per_s": ok_forms[bf16_best]["cells_pulses_per_s"],
+            "ms": ok_forms[bf16_best]["ms"], "rel_err": ok_forms[bf16_best]["rel_err"],
+            "speedup_vs_f32": round(ok_forms[bf16_best]["cells_pulses_per_s"] / f32_rate, 2),
+            "roofline_frac": ok_forms[bf16_best]["roofline_frac"],
+            "executed_frac": ok_forms[bf16_best]["executed_frac"]},
     }
     print(json.dumps(out), flush=True)
 
@@ -636,13 +688,13 @@ def bench_kt(args):
     echo = torch.from_numpy(case["echo"]).cuda()
     cells = plan.n_coarse
     cp_total = float(cells) * plan.rows * plan.n_fine * plan.M
-    gamma2 = plan.threshold(1.0, 1e-9)
+    pfa = 1e-9
     pm = torch.empty((cells, plan.rows), dtype=torch.float32, device="cuda")
     af = torch.empty((cells, plan.rows), dtype=torch.int32, device="cuda")
 
     def step():
         plan.search(echo, "f32fft", 1, out=(pm, af))
-        return plan.detect(pm, af, gamma2, cap=4096)
+        return plan.detect(pm, af, pfa, 1.0, cap=4096)
     log(f"DS-KT-MFP plan: {plan.kt_folds} folds x {plan.K[1]} coarse accelerations = "
         f"{cells} cells x {plan.n_fine} fine x {plan.rows} rows, N'={plan.fd_pad}; "
         f"workspace {plan.workspace_bytes / 2**20:.0f} MiB")
@@ -661,7 +713,7 @@ def bench_kt(args):
     ms = (t1 - t0) * 1e3 / args.steps
     value = cp_total / (ms * 1e-3)
     log(f"timed {args.steps} steps: {ms:.1f} ms/step, {value:.3e} cells*pulses/s")
-    _, count, best = plan.detect(pm, af, gamma2, cap=4096)
+    _, count, best = plan.detect(pm, af, pfa, 1.0, cap=4096)
     nl = max(prof["fine_launches"], 1)
     fine_avg_s = prof["fine_ms"] / nl * 1e-3
     flops_launch = prof["fine_cell_pulses"] / nl / (plan.M * plan.n_fine) * plan.R \

@@ -88,7 +88,7 @@ typedef enum {
   DSGRFT_FORM_BF16_GLO = 6, /* bf16, split 2 only: Fh Gh + Fh Gl, the
                               gathered rows split into hi + lo and the fine
                               table not (the other order of split 2) */
-  DSGRFT_FORM_F16_SYM = 7  /* fp16, split 1, the fine cells taken in
+  DSGRFT_FORM_F16_SYM = 7, /* fp16, split 1, the fine cells taken in
                               conjugate pairs: the fine offsets are symmetric
                               about the coarse centre and the fine phase
                               (eq. (44)) is linear in them, so the cell at
@@ -96,6 +96,12 @@ typedef enum {
                               the four real products Fr Gr, Fi Gi, Fr Gi,
                               Fi Gr of the +d column give both cells.  Same
                               operands and rounding as F16 split 1; not for
+                              DS-KT-MFP plans */
+  DSGRFT_FORM_BF16_SYM = 8 /* bf16 over the conjugate pairs of F16_SYM,
+                              split 2: Fh Gh + Fh Gl (the products of
+                              BF16_GLO), split 3: + Fl Gh (those of BF16
+                              split 3); every part accumulates into the same
+                              four real products of a pair; not for
                               DS-KT-MFP plans */
 } dsgrft_form;
 
@@ -194,6 +200,12 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
  * Accepts NULL. */
 void dsgrft_plan_destroy(dsgrft_plan plan);
 
+/* The plan's derived quantities (Sec. II-B and Sec. IV-B: wavelength, range
+ * bin, integration time, the fine steps of eqs. (39)-(42) with alpha_p = 1,
+ * the coarse cells per order of the dual-scale lattice, eqs. (48)-(52), and
+ * the fine cells per coarse cell, eq. (52)), as defined in the header
+ * comment and dsgrft_plan_info above.  Host-only; E_INVALID for NULL
+ * arguments. */
 dsgrft_status dsgrft_plan_get_info(dsgrft_plan plan, dsgrft_plan_info *out);
 
 /* Static text for a status code (never NULL). */
@@ -230,7 +242,7 @@ dsgrft_status dsgrft_mgift(dsgrft_plan plan, const void *d_echo,
  * caller's buffers) or, when d_cells is NULL,
  * cc_begin..cc_begin+n-1.  Outputs d_pmax, d_argf: [n][rows] (float, int32).
  * `form`/`split`: see dsgrft_form; FP32, FFT, F16_3M and F16_SYM require split = 1,
- * BF16_GLO split = 2 (else E_INVALID).  The echo must
+ * BF16_GLO split = 2, BF16_SYM split 2 or 3 (else E_INVALID).  The echo must
  * stay unchanged until the stream reaches the end of this call. */
 dsgrft_status dsgrft_search(dsgrft_plan plan, dsgrft_form form, int32_t split,
                             const void *d_echo, const int64_t *d_cells,
@@ -254,26 +266,49 @@ dsgrft_status dsgrft_grft(dsgrft_plan plan, const void *d_echo,
                           int64_t cc_begin, int64_t n, float *d_pmax,
                           int32_t *d_argf, float *d_power, void *stream);
 
-/* Mean |s|^2 of the echo (noise power estimate for the threshold), written
- * to d_sigma2 (one double). */
+/* Noise power sigma^2 of the LRT threshold (Sec. III-C, eq. (33)): the
+ * threshold is written for the noise of the K range-frequency bins; on a
+ * range-compressed echo those bins are folded into the per-sample noise
+ * power, estimated here as the mean of |s[m][n]|^2 over all M N samples
+ * (FP64 partial sums of 65536 samples, summed in a fixed order; the
+ * estimator itself is not in the paper, and the targets' energy biases it
+ * upward by their share of the total).  Writes one double to d_sigma2. */
 dsgrft_status dsgrft_noise_power(dsgrft_plan plan, const void *d_echo,
                                  double *d_sigma2, void *stream);
 
+/* LRT threshold on |Y|^2 (Sec. III-C, eqs. (31), (33)): gamma^2 =
+ * -M sigma^2 ln P_FA, evaluated in FP64 as (-M sigma^2) ln P_FA, the K
+ * frequency bins of eq. (33) folded into sigma^2 (see dsgrft_noise_power).
+ * Host-only.  E_INVALID unless sigma2 is finite and >= 0 and 0 < pfa < 1. */
+dsgrft_status dsgrft_lrt_threshold(dsgrft_plan plan, double sigma2, double pfa,
+                                   double *h_gamma2);
+
 /* LRT detection (Sec. III-C, eqs. (31), (33); Alg. 3): entries of a reduced
  * map [n][rows] (cells cc_begin.. or d_cells as in dsgrft_search) with power
- * > gamma2 are listed in flat order (cell, then row) into d_peaks[0..cap) with
- * their parameters (eq. (72), kappa = 1).  *d_count receives the number of
- * entries above the threshold (may exceed cap).  d_best receives the global
- * maximum (smallest flat index on ties), regardless of the threshold.  For
- * the LRT threshold use gamma2 = -M sigma^2 ln P_FA.  No status reports
- * overflow because the count is only known on the device; compare
- * *d_count with cap after the stream completes. */
+ * > gamma^2 = -M sigma^2 ln P_FA (FP64, as in dsgrft_lrt_threshold) are
+ * listed in flat order (cell, then row) into d_peaks[0..cap) with their
+ * parameters (eq. (72), kappa = 1).  sigma^2 is *d_sigma2 when d_sigma2 is
+ * not NULL (a device double, e.g. written by dsgrft_noise_power earlier on
+ * the same stream; a NaN there yields no detection), else `sigma2`.
+ * *d_count (device) receives the number of entries above the threshold,
+ * which may exceed cap (only the first cap are written).  d_best (device,
+ * may be NULL) receives the global maximum (smallest flat index on ties),
+ * whatever the threshold.
+ * h_count: NULL, or a host int32.  When set, the call waits until `stream`
+ * has completed, stores the count there and returns DSGRFT_E_CAPACITY if it
+ * exceeds cap (the outputs are complete otherwise); when NULL the call does
+ * not synchronise and cannot report overflow (compare *d_count with cap
+ * once the stream has completed).
+ * E_INVALID for NULL map/count pointers, n < 1, cap < 0, d_peaks NULL with
+ * cap > 0, pfa outside (0, 1), or (without d_sigma2) sigma2 negative or not
+ * finite. */
 dsgrft_status dsgrft_detect(dsgrft_plan plan, const float *d_pmax,
                             const int32_t *d_argf, const int64_t *d_cells,
-                            int64_t cc_begin, int64_t n, double gamma2,
+                            int64_t cc_begin, int64_t n, double sigma2,
+                            const double *d_sigma2, double pfa,
                             dsgrft_peak *d_peaks, int32_t cap,
                             int32_t *d_count, dsgrft_peak *d_best,
-                            void *stream);
+                            int32_t *h_count, void *stream);
 
 /* Cell-averaging CFAR along range on a reduced map (a detector beside the
  * paper's fixed LRT threshold, not in the paper): entry (cell, row r) is a
@@ -283,14 +318,15 @@ dsgrft_status dsgrft_detect(dsgrft_plan plan, const float *d_pmax,
  * the number of such rows, and an entry without any is never a detection.
  * For exponentially distributed noise power and Nt = 2 train interior
  * training rows, alpha = Nt (P_FA^(-1/Nt) - 1) gives false-alarm probability
- * P_FA.  Map, cells, outputs and d_best as in dsgrft_detect; guard >= 0,
- * 1 <= train, both <= 65536, alpha finite and >= 0, else E_INVALID. */
+ * P_FA.  Map, cells, outputs, d_best and h_count (E_CAPACITY) as in
+ * dsgrft_detect; guard >= 0, 1 <= train, both <= 65536, alpha finite and
+ * >= 0, else E_INVALID. */
 dsgrft_status dsgrft_detect_cfar(dsgrft_plan plan, const float *d_pmax,
                                  const int32_t *d_argf, const int64_t *d_cells,
                                  int64_t cc_begin, int64_t n, int32_t guard,
                                  int32_t train, double alpha, dsgrft_peak *d_peaks,
                                  int32_t cap, int32_t *d_count, dsgrft_peak *d_best,
-                                 void *stream);
+                                 int32_t *h_count, void *stream);
 
 /* Continuous objective for off-grid refinement (not in the paper; see the
  * oracle for the definition): for candidates theta[b] = (r0, v, a) (device
@@ -333,13 +369,18 @@ dsgrft_status dsgrft_refine(dsgrft_plan plan, const void *d_echo,
  * end synchronises the device, sums the event durations and destroys the
  * events.  Algorithmic work per launch: gather bytes = units x rows x M x
  * (8 read + bytes per gathered sample written); fine flops = 8 per
- * cell-pulse (one complex multiply-add), independent of the split. */
+ * cell-pulse (one complex multiply-add), independent of the split.
+ * Executed matrix work (MFMA forms; 0 for the FP32 and FFT forms): the
+ * padded rows x padded table columns x padded pulses x 2 flops x the real
+ * products taken per (row, column, pulse): 4 per split part, 3 for F16_3M,
+ * and per conjugate-pair column 4 (F16_SYM) or 4 per split part (BF16_SYM). */
 typedef struct {
   int64_t gather_launches, fine_launches;  /* timed launches               */
   double gather_ms, fine_ms;               /* summed durations            */
   double gather_bytes;                     /* algorithmic bytes, timed    */
   double fine_flops;                       /* algorithmic flops, timed    */
   double fine_cell_pulses;                 /* cells x pulses, timed       */
+  double fine_mfma_flops;                  /* executed MFMA flops, timed  */
 } dsgrft_profile;
 
 dsgrft_status dsgrft_profile_begin(dsgrft_plan plan, int32_t capacity);

@@ -18,7 +18,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory",
           3: "HIP runtime error", 4: "unsupported request",
           5: "output capacity exceeded"}
 
-FORMS = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "f32fft": 4, "f16_3m": 5, "bf16_glo": 6, "f16_sym": 7}
+FORMS = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "f32fft": 4, "f16_3m": 5, "bf16_glo": 6, "f16_sym": 7,
+         "bf16_sym": 8}
 
 
 class DsgrftError(RuntimeError):
@@ -55,7 +56,7 @@ class Profile(C.Structure):
     _fields_ = [("gather_launches", C.c_int64), ("fine_launches", C.c_int64),
                 ("gather_ms", C.c_double), ("fine_ms", C.c_double),
                 ("gather_bytes", C.c_double), ("fine_flops", C.c_double),
-                ("fine_cell_pulses", C.c_double)]
+                ("fine_cell_pulses", C.c_double), ("fine_mfma_flops", C.c_double)]
 
 
 PEAK_DTYPE = np.dtype({
@@ -86,8 +87,11 @@ def lib():
         "dsgrft_search_full": [vp, C.c_int, i32, vp, i64, i64, vp, vp],
         "dsgrft_grft": [vp, vp, i64, i64, vp, vp, vp, vp],
         "dsgrft_noise_power": [vp, vp, vp, vp],
-        "dsgrft_detect": [vp, vp, vp, vp, i64, i64, dbl, vp, i32, vp, vp, vp],
-        "dsgrft_detect_cfar": [vp, vp, vp, vp, i64, i64, i32, i32, dbl, vp, i32, vp, vp, vp],
+        "dsgrft_lrt_threshold": [vp, dbl, dbl, C.POINTER(dbl)],
+        "dsgrft_detect": [vp, vp, vp, vp, i64, i64, dbl, vp, dbl, vp, i32, vp, vp,
+                          C.POINTER(i32), vp],
+        "dsgrft_detect_cfar": [vp, vp, vp, vp, i64, i64, i32, i32, dbl, vp, i32, vp, vp,
+                               C.POINTER(i32), vp],
         "dsgrft_adjoint_forward": [vp, vp, vp, i32, vp, vp, vp],
         "dsgrft_adjoint_backward": [vp, vp, vp, i32, vp, vp, vp, vp, vp],
         "dsgrft_refine": [vp, vp, vp, i32, i32, vp, vp],
@@ -116,7 +120,8 @@ def exported_symbols():
     return ["dsgrft_plan_create", "dsgrft_plan_destroy", "dsgrft_plan_get_info",
             "dsgrft_status_string", "dsgrft_coarse_tables", "dsgrft_mgift",
             "dsgrft_search", "dsgrft_search_full", "dsgrft_grft",
-            "dsgrft_noise_power", "dsgrft_detect", "dsgrft_detect_cfar",
+            "dsgrft_noise_power", "dsgrft_lrt_threshold", "dsgrft_detect",
+            "dsgrft_detect_cfar",
             "dsgrft_adjoint_forward",
             "dsgrft_adjoint_backward", "dsgrft_refine",
             "dsgrft_profile_begin", "dsgrft_profile_end"]

@@ -44,7 +44,7 @@ hipError_t dalloc(T **p, size_t bytes, size_t &total) {
 
 void release(dsgrft_plan p) {
   if (!p) return;
-  void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->FS16, p->sym_cols, p->u_off, p->u_psi,
+  void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->FS16, p->FSB16, p->sym_cols, p->u_off, p->u_psi,
                   p->Gbuf[0], p->gscbuf[0], p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
                   p->kt_spec, p->kt_invd, p->packed, p->det_ws, p->adj_ws};
   for (void *b : bufs)
@@ -63,7 +63,7 @@ bool on_plan_device(dsgrft_plan p) {
 
 dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
   if (p->kt && form != DSGRFT_FORM_F32_FFT)
-    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_F16_SYM) ? DSGRFT_E_UNSUPPORTED
+    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_BF16_SYM) ? DSGRFT_E_UNSUPPORTED
                                                                     : DSGRFT_E_INVALID;
   switch (form) {
     case DSGRFT_FORM_F32:
@@ -76,6 +76,8 @@ dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_BF16_GLO:
       return split == 2 ? DSGRFT_OK : DSGRFT_E_INVALID;
+    case DSGRFT_FORM_BF16_SYM:
+      return (split == 2 || split == 3) ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_F16:
     case DSGRFT_FORM_BF16:
     case DSGRFT_FORM_FP8:
@@ -89,8 +91,27 @@ dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
 // of G from split 3 on, and in BF16_GLO) of 2-byte or 1-byte components.
 double gather_bytes(dsgrft_form form, int split) {
   if (form == DSGRFT_FORM_F32 || form == DSGRFT_FORM_F32_FFT) return 8.0;
-  const double planes = (split >= 3 || form == DSGRFT_FORM_BF16_GLO) ? 4.0 : 2.0;
+  const double planes =
+      (split >= 3 || form == DSGRFT_FORM_BF16_GLO || form == DSGRFT_FORM_BF16_SYM) ? 4.0 : 2.0;
   return planes * (form == DSGRFT_FORM_FP8 ? 1.0 : 2.0);
+}
+
+// Executed MFMA flops per gathered unit of a fine-search launch: padded rows
+// x table columns x padded pulses x 2 x real products per (row, column,
+// pulse); 0 for the vector-ALU forms.
+double mfma_flops_per_unit(dsgrft_plan p, dsgrft_form form, int split) {
+  double prod, cols = (double)p->Cp;
+  switch (form) {
+    case DSGRFT_FORM_F16:
+    case DSGRFT_FORM_BF16:
+    case DSGRFT_FORM_FP8: prod = 4.0 * split; break;
+    case DSGRFT_FORM_BF16_GLO: prod = 8.0; break;
+    case DSGRFT_FORM_F16_3M: prod = 3.0; break;
+    case DSGRFT_FORM_F16_SYM: prod = 4.0; cols = 32.0 * p->FBs; break;
+    case DSGRFT_FORM_BF16_SYM: prod = 4.0 * split; cols = 32.0 * p->FBs; break;
+    default: return 0.0;
+  }
+  return (double)p->rows_p * cols * (double)p->Mp * 2.0 * prod;
 }
 
 // Stages a0..a4 over n listed cells, batch by batch.  pmax/argf may be NULL
@@ -163,6 +184,7 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
         pr.nf++;
         pr.fcp += samples * p->C;
         pr.fflops += 8.0 * samples * p->C;
+        pr.fxflops += (double)nu * mfma_flops_per_unit(p, form, split);
       }
       DS_TRY(hipEventRecord(p->ev_f[slot], s));
     }
@@ -407,6 +429,7 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
       dalloc(&p->FBF16, f16b, tot) != hipSuccess ||
       dalloc(&p->F8, f16b ? (size_t)4 * p->Cp * p->Mp : 0, tot) != hipSuccess ||
       dalloc(&p->FS16, (size_t)2 * p->FBs * p->KB * 64 * sizeof(uint4), tot) != hipSuccess ||
+      dalloc(&p->FSB16, (size_t)4 * p->FBs * p->KB * 64 * sizeof(uint4), tot) != hipSuccess ||
       dalloc(&p->sym_cols, 2 * sym_cols_n * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->gscbuf[0], 2 * (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
       (fft_form_supported(M) &&
@@ -593,26 +616,51 @@ dsgrft_status dsgrft_noise_power(dsgrft_plan p, const void *d_echo, double *d_si
   return DSGRFT_OK;
 }
 
+// Count readback of the detection calls: with h_count set, wait for the
+// stream, store the count and report E_CAPACITY when it exceeds cap.
+static dsgrft_status read_count(const int32_t *d_count, int32_t cap, int32_t *h_count,
+                                hipStream_t s) {
+  if (!h_count) return DSGRFT_OK;
+  int32_t c = 0;
+  DS_TRY(hipMemcpyAsync(&c, d_count, sizeof(c), hipMemcpyDeviceToHost, s));
+  DS_TRY(hipStreamSynchronize(s));
+  *h_count = c;
+  return c > cap ? DSGRFT_E_CAPACITY : DSGRFT_OK;
+}
+
+dsgrft_status dsgrft_lrt_threshold(dsgrft_plan p, double sigma2, double pfa,
+                                   double *h_gamma2) {
+  if (!p || !h_gamma2 || !std::isfinite(sigma2) || sigma2 < 0.0 || !(pfa > 0.0) ||
+      !(pfa < 1.0))
+    return DSGRFT_E_INVALID;
+  *h_gamma2 = (-(double)p->M * sigma2) * std::log(pfa);
+  return DSGRFT_OK;
+}
+
 dsgrft_status dsgrft_detect(dsgrft_plan p, const float *d_pmax, const int32_t *d_argf,
                             const int64_t *d_cells, int64_t cc_begin, int64_t n,
-                            double gamma2, dsgrft_peak *d_peaks, int32_t cap,
-                            int32_t *d_count, dsgrft_peak *d_best, void *stream) {
+                            double sigma2, const double *d_sigma2, double pfa,
+                            dsgrft_peak *d_peaks, int32_t cap, int32_t *d_count,
+                            dsgrft_peak *d_best, int32_t *h_count, void *stream) {
   if (!p || !d_pmax || !d_argf || !d_count || n < 1 || cap < 0) return DSGRFT_E_INVALID;
   if (cap > 0 && !d_peaks) return DSGRFT_E_INVALID;
-  if (!std::isfinite(gamma2) && !std::isinf(gamma2)) return DSGRFT_E_INVALID;
+  if (!d_sigma2 && (!std::isfinite(sigma2) || sigma2 < 0.0)) return DSGRFT_E_INVALID;
+  if (!(pfa > 0.0) || !(pfa < 1.0)) return DSGRFT_E_INVALID;
   if (!d_cells && (cc_begin < 0 || cc_begin + n > p->n_coarse)) return DSGRFT_E_INVALID;
   if (n > p->n_coarse || (double)n * p->rows > 2147483647.0) return DSGRFT_E_INVALID;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
-  DS_TRY(launch_detect(p, d_pmax, d_argf, d_cells, cc_begin, n, gamma2, d_peaks, cap,
-                       d_count, d_best, (hipStream_t)stream));
-  return DSGRFT_OK;
+  hipStream_t s = (hipStream_t)stream;
+  DS_TRY(launch_detect(p, d_pmax, d_argf, d_cells, cc_begin, n, sigma2, d_sigma2,
+                       std::log(pfa), d_peaks, cap, d_count, d_best, s));
+  return read_count(d_count, cap, h_count, s);
 }
 
 dsgrft_status dsgrft_detect_cfar(dsgrft_plan p, const float *d_pmax,
                                  const int32_t *d_argf, const int64_t *d_cells,
                                  int64_t cc_begin, int64_t n, int32_t guard, int32_t train,
                                  double alpha, dsgrft_peak *d_peaks, int32_t cap,
-                                 int32_t *d_count, dsgrft_peak *d_best, void *stream) {
+                                 int32_t *d_count, dsgrft_peak *d_best, int32_t *h_count,
+                                 void *stream) {
   if (!p || !d_pmax || !d_argf || !d_count || n < 1 || cap < 0) return DSGRFT_E_INVALID;
   if (cap > 0 && !d_peaks) return DSGRFT_E_INVALID;
   if (guard < 0 || train < 1 || guard > 65536 || train > 65536) return DSGRFT_E_INVALID;
@@ -620,9 +668,10 @@ dsgrft_status dsgrft_detect_cfar(dsgrft_plan p, const float *d_pmax,
   if (!d_cells && (cc_begin < 0 || cc_begin + n > p->n_coarse)) return DSGRFT_E_INVALID;
   if (n > p->n_coarse || (double)n * p->rows > 2147483647.0) return DSGRFT_E_INVALID;
   if (!on_plan_device(p)) return DSGRFT_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
   DS_TRY(launch_detect_cfar(p, d_pmax, d_argf, d_cells, cc_begin, n, guard, train, alpha,
-                            d_peaks, cap, d_count, d_best, (hipStream_t)stream));
-  return DSGRFT_OK;
+                            d_peaks, cap, d_count, d_best, s));
+  return read_count(d_count, cap, h_count, s);
 }
 
 dsgrft_status dsgrft_adjoint_forward(dsgrft_plan p, const void *d_echo,
@@ -728,6 +777,7 @@ dsgrft_status dsgrft_profile_end(dsgrft_plan p, dsgrft_profile *out) {
   out->gather_bytes = pr.gbytes;
   out->fine_flops = pr.fflops;
   out->fine_cell_pulses = pr.fcp;
+  out->fine_mfma_flops = pr.fxflops;
   prof_free(p);
   return DSGRFT_OK;
 }

@@ -32,10 +32,17 @@ __device__ inline bool better(float v, int64_t i, float bv, int64_t bi) {
 }
 
 // Detection tests on entry i of a reduced map.
+//
+// LRT (eq. (33)): power > gamma^2 = -M sigma^2 ln P_FA, formed in FP64 in
+// the order (-M sigma^2) ln P_FA; ln P_FA comes from the host (one value per
+// call), sigma^2 from the host or, when s2p is set, from device memory (an
+// estimate written earlier on the same stream).
 struct LrtTest {
-  double gamma2;
+  double neg_m, s2, ln_pfa;
+  const double *s2p;
   __device__ bool operator()(const float *__restrict__ pm, int64_t i) const {
-    return (double)pm[i] > gamma2;
+    const double sigma2 = s2p != nullptr ? *s2p : s2;
+    return (double)pm[i] > (neg_m * sigma2) * ln_pfa;
   }
 };
 
@@ -289,10 +296,12 @@ hipError_t launch_detect_t(dsgrft_plan p, const float *pmax, const int32_t *argf
 
 hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
                          const int64_t *cells, int64_t cc_begin, int64_t n,
-                         double gamma2, dsgrft_peak *peaks, int32_t cap,
-                         int32_t *count, dsgrft_peak *best, hipStream_t s) {
-  return launch_detect_t(p, pmax, argf, cells, cc_begin, n, LrtTest{gamma2}, peaks, cap,
-                         count, best, s);
+                         double sigma2, const double *d_sigma2, double ln_pfa,
+                         dsgrft_peak *peaks, int32_t cap, int32_t *count,
+                         dsgrft_peak *best, hipStream_t s) {
+  const LrtTest test{-(double)p->M, sigma2, ln_pfa, d_sigma2};
+  return launch_detect_t(p, pmax, argf, cells, cc_begin, n, test, peaks, cap, count, best,
+                         s);
 }
 
 hipError_t launch_detect_cfar(dsgrft_plan p, const float *pmax, const int32_t *argf,

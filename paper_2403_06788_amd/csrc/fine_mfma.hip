@@ -604,8 +604,8 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
   }
 }
 
-// The fp16 search over conjugate pairs of fine cells.  A fine cell's offsets
-// d from the coarse centre are symmetric about it (R/2 on either side, for
+// The search over conjugate pairs of fine cells.  A fine cell's offsets d
+// from the coarse centre are symmetric about it (R/2 on either side, for
 // even R one more on the negative side) and its phase is linear in d, so the
 // cell at -d has the conjugate fine phasor of the cell at +d.  With the four
 // real products of the +d column, Prr = Fr Gr, Pii = Fi Gi, Pri = Fr Gi,
@@ -619,19 +619,46 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
 // even R, and the centre), ordered by cols[c] (the +d cell) and
 // cols[ncols + c] (the -d cell, -1 if none); padding columns are zero.
 //
+// The bf16 forms add split parts; the four products are linear in both
+// operands, so every part accumulates into the same four sets:
+//   NPF = 2, NPG = 4: Fh Gh + Fh Gl (the gathered rows split into hi + lo),
+//     16 MFMAs per K step and wave for 64 cells x 64 rows (32 in
+//     k_fine_mfma<bf16, rows split>);
+//   NPF = 4, NPG = 4: + Fl Gh (the table's lo part; Fl(-d) is the conjugate
+//     of Fl(+d) as well, rounding being symmetric), 24 MFMAs (48 in
+//     k_fine_mfma<bf16, 3>).
+// Within a step, every product part runs over all eight accumulators before
+// the next part.
+//
 // Tile: 64 columns x 128 rows per workgroup, 32 columns x 64 rows per wave (1
-// x 2 blocks of 32x32x16), four accumulator sets (128 registers, 167 in
-// all); 12 KiB stages in a ring of four LDS slots filled by LDS-DMA a pair of
-// K steps ahead, one barrier per pair, as in k_fine_mfma3.  Three workgroups
-// share a CU (144 KiB of LDS, three waves per SIMD).  Tiles are grouped by
-// four row tiles (GN = 4; 8 and 16 were 3% and 9% slower, 2 and 6 within 1%).
-__global__ __launch_bounds__(256, 3) void k_fine_mfma_sym(
+// x 2 blocks of 32x32x16), four accumulator sets (128 registers; 167 in all
+// for the fp16 form).  Stages of 2 NPF column and 4 NPG row fragments (12, 20
+// or 24 KiB) are filled by LDS-DMA into a ring: four slots a pair of K steps
+// ahead with one barrier per pair (as in k_fine_mfma3) when the ring fits
+// beside the other workgroups of the CU, else three slots two steps ahead
+// with one barrier per step.  Workgroups per CU: three (fp16, 144 KiB of
+// LDS, three waves per SIMD) or two (bf16; 160 and 144 KiB).  Tiles are
+// grouped by four row tiles (GN = 4; for the fp16 form, 8 and 16 were 3% and
+// 9% slower, 2 and 6 within 1%).
+template <int NPF, int NPG>
+struct SymCfg {
+  static constexpr int NFR = 2 * NPF + 4 * NPG;    // fragments per stage
+  static constexpr int CH = NFR * 64, CPT = CH / 256;
+  static constexpr int WG = NPG == 2 ? 3 : 2;      // workgroups per CU
+  static constexpr int NST = WG * 4 * CH * 16 <= 160 * 1024 ? 4 : 3;
+  static_assert(CH % 256 == 0, "stage must split evenly over 256 threads");
+  static_assert(WG * NST * CH * 16 <= 160 * 1024, "rings exceed LDS");
+};
+
+template <class Op, int NPF, int NPG>
+__global__ __launch_bounds__(256, (SymCfg<NPF, NPG>::WG)) void k_fine_mfma_sym(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
     const int32_t *__restrict__ cols, unsigned long long *__restrict__ packed,
     float *__restrict__ full, int FBs, int NB, int KS, int64_t nunits, int64_t unit0,
     int R3, int C, int rows, int GN) {
-  constexpr int NST = 4, NBG = 4, NFB = 2;     // row / column blocks per tile
-  constexpr int CH = 12 * 64, CPT = CH / 256;  // 12 fragments per stage
+  using SC = SymCfg<NPF, NPG>;
+  constexpr int NST = SC::NST, CH = SC::CH, CPT = SC::CPT;
+  constexpr int NBG = 4, NFB = 2;  // row / column blocks per tile
   __shared__ uint4 lds[NST][CH];
 
   const int NT = NB / NBG, FT = FBs / NFB;
@@ -640,19 +667,20 @@ __global__ __launch_bounds__(256, 3) void k_fine_mfma_sym(
   const int wf = wave & 1, wn = wave >> 1;
   const int wbase = tid & ~63;
 
-  // Chunk c of a stage: lane c % 64, fragment c / 64: columns (re 0-1, im
-  // 2-3), then rows (re 4-7, im 8-11).
+  // Chunk c of a stage: lane c % 64, fragment c / 64: columns, NFB per plane
+  // (re_hi, im_hi[, re_lo, im_lo]), then rows, NBG per plane (re_hi,
+  // im_hi[, re_lo, im_lo]).
   const uint4 *src[CPT];
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
     const int c = tid + 256 * j;
     const int ln = c & 63, fi = c >> 6;
-    if (fi < 4) {
-      const int plane = fi >> 1, blk = fi & 1;
+    if (fi < NFB * NPF) {
+      const int plane = fi / NFB, blk = fi % NFB;
       src[j] = F + (((int64_t)plane * FBs + tm.ft * NFB + blk) * KS) * 64 + ln;
     } else {
-      const int plane = (fi - 4) >> 2, blk = (fi - 4) & 3;
-      src[j] = G + (((tm.u * 2 + plane) * NB + tm.nt * NBG + blk) * (int64_t)KS) * 64 + ln;
+      const int plane = (fi - NFB * NPF) / NBG, blk = (fi - NFB * NPF) % NBG;
+      src[j] = G + (((tm.u * NPG + plane) * NB + tm.nt * NBG + blk) * (int64_t)KS) * 64 + ln;
     }
   }
   auto issue = [&](int stage) {
@@ -682,34 +710,60 @@ __global__ __launch_bounds__(256, 3) void k_fine_mfma_sym(
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[q][j] = f16v{};
 
-  auto step = [&](int kt) {
-    const uint4 *slot = lds[kt % NST];
-    const uint4 fr = slot[wf * 64 + lane], fi = slot[(2 + wf) * 64 + lane];
-    uint4 gr[2], gi[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) gr[j] = slot[(4 + wn * 2 + j) * 64 + lane];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) gi[j] = slot[(8 + wn * 2 + j) * 64 + lane];
+  // One product part: fr/fi a column fragment pair, gr/gi the row fragments.
+  auto part = [&](const Frag<1> &fr, const Frag<1> &fi, const Frag<1> (&gr)[2],
+                  const Frag<1> (&gi)[2]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      acc[0][j] = OpF16::mma({{fr}}, {{gr[j]}}, acc[0][j], 0, 0);
-      acc[1][j] = OpF16::mma({{fi}}, {{gi[j]}}, acc[1][j], 0, 0);
-      acc[2][j] = OpF16::mma({{fr}}, {{gi[j]}}, acc[2][j], 0, 0);
-      acc[3][j] = OpF16::mma({{fi}}, {{gr[j]}}, acc[3][j], 0, 0);
+      acc[0][j] = Op::mma(fr, gr[j], acc[0][j], 0, 0);
+      acc[1][j] = Op::mma(fi, gi[j], acc[1][j], 0, 0);
+      acc[2][j] = Op::mma(fr, gi[j], acc[2][j], 0, 0);
+      acc[3][j] = Op::mma(fi, gr[j], acc[3][j], 0, 0);
     }
+  };
+  auto step = [&](int kt) {
+    const uint4 *slot = lds[kt % NST];
+    Frag<1> f[NPF / 2][2], g[NPG / 2][2][2];  // [hi/lo][re/im]([row block])
+#pragma unroll
+    for (int h = 0; h < NPF / 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) f[h][c] = {{slot[((2 * h + c) * NFB + wf) * 64 + lane]}};
+#pragma unroll
+    for (int h = 0; h < NPG / 2; ++h)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          g[h][c][j] = {{slot[(NFB * NPF + (2 * h + c) * NBG + wn * 2 + j) * 64 + lane]}};
+    part(f[0][0], f[0][1], g[0][0], g[0][1]);  // Fh Gh
+    if (NPG == 4) part(f[0][0], f[0][1], g[NPG / 2 - 1][0], g[NPG / 2 - 1][1]);  // Fh Gl
+    if (NPF == 4) part(f[NPF / 2 - 1][0], f[NPF / 2 - 1][1], g[0][0], g[0][1]);  // Fl Gh
   };
 
   const int nkt = KS;
-  issue(0);
-  issue(1);
-  for (int kt = 0; kt < nkt; kt += 2) {
-    wait_copies_barrier<CPT>(0);
-    if (kt + 2 < nkt) {
-      issue(kt + 2);
-      issue(kt + 3);
+  if (NST == 4) {
+    issue(0);
+    issue(1);
+    for (int kt = 0; kt < nkt; kt += 2) {
+      wait_copies_barrier<CPT>(0);
+      if (kt + 2 < nkt) {
+        issue(kt + 2);
+        issue(kt + 3);
+      }
+      step(kt);
+      step(kt + 1);
     }
-    step(kt);
-    step(kt + 1);
+  } else {
+    // three slots: step kt's stage is awaited with step kt + 1's in flight;
+    // the slot refilled after the barrier was last read in step kt - 1,
+    // which every wave finished before it
+    issue(0);
+    if (nkt > 1) issue(1);
+    for (int kt = 0; kt < nkt; ++kt) {
+      wait_copies_barrier<CPT>(kt + 1 < nkt ? 1 : 0);
+      if (kt + 2 < nkt) issue(kt + 2);
+      step(kt);
+    }
   }
 
   // ---- epilogue: both cells of each column ---------------------------------
@@ -821,15 +875,24 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
                          p->NB, p->Mp / OpF16::KSTEP, nunits, unit0, p->R3, p->C, p->rows, 8);
       return hipGetLastError();
     }
-    case DSGRFT_FORM_F16_SYM: {
-      if (split != 1 || (p->Mp / OpF16::KSTEP) % 2 != 0 || p->FBs <= 0 || p->FBs % 2 != 0 ||
-          p->NB % 4 != 0)
+    case DSGRFT_FORM_F16_SYM:
+    case DSGRFT_FORM_BF16_SYM: {
+      const bool b = form == DSGRFT_FORM_BF16_SYM;
+      if ((b ? (split != 2 && split != 3) : split != 1) || (p->Mp / OpF16::KSTEP) % 2 != 0 ||
+          p->FBs <= 0 || p->FBs % 2 != 0 || p->NB % 4 != 0)
         return hipErrorInvalidValue;
       const int64_t tiles = nunits * (p->NB / 4) * (p->FBs / 2);
-      hipLaunchKernelGGL(k_fine_mfma_sym, dim3((unsigned)tiles), dim3(256), 0, s,
-                         (const uint4 *)p->FS16, (const uint4 *)p->G, p->sym_cols, p->packed,
-                         full, p->FBs, p->NB, p->Mp / OpF16::KSTEP, nunits, unit0, p->R3, p->C,
-                         p->rows, 4);
+#define DS_SYM(OP, NPF, NPG, TAB)                                                       \
+  hipLaunchKernelGGL((k_fine_mfma_sym<OP, NPF, NPG>), dim3((unsigned)tiles), dim3(256), 0, s, \
+                     (const uint4 *)(TAB), (const uint4 *)p->G, p->sym_cols, p->packed, full, \
+                     p->FBs, p->NB, p->Mp / OP::KSTEP, nunits, unit0, p->R3, p->C, p->rows, 4)
+      if (!b)
+        DS_SYM(OpF16, 2, 2, p->FS16);
+      else if (split == 2)
+        DS_SYM(OpBF16, 2, 4, p->FSB16);
+      else
+        DS_SYM(OpBF16, 4, 4, p->FSB16);
+#undef DS_SYM
       return hipGetLastError();
     }
     case DSGRFT_FORM_BF16:

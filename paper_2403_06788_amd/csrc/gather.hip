@@ -291,8 +291,8 @@ hipError_t launch_mgift_out(dsgrft_plan p, GatherSrc src, int64_t nunits,
 hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
                             GatherSrc src, int64_t nunits, hipStream_t s) {
   // G's lo planes enter from split 3 on (split 2 adds the fine table's lo)
-  // and in BF16_GLO
-  const bool lo = split >= 3 || form == DSGRFT_FORM_BF16_GLO;
+  // and in BF16_GLO and BF16_SYM
+  const bool lo = split >= 3 || form == DSGRFT_FORM_BF16_GLO || form == DSGRFT_FORM_BF16_SYM;
   uint4 *G = (uint4 *)p->G;
   if (form == DSGRFT_FORM_FP8) {
     dim3 grid((unsigned)(nunits * p->NB));
@@ -318,7 +318,8 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
                      src.unit_stride, p->NB, p->KB, nunits, G)
   if (form == DSGRFT_FORM_F16 || form == DSGRFT_FORM_F16_3M || form == DSGRFT_FORM_F16_SYM) {
     if (!lo) DS_GATHER_LP(_Float16, 2); else DS_GATHER_LP(_Float16, 4);
-  } else if (form == DSGRFT_FORM_BF16 || form == DSGRFT_FORM_BF16_GLO) {
+  } else if (form == DSGRFT_FORM_BF16 || form == DSGRFT_FORM_BF16_GLO ||
+             form == DSGRFT_FORM_BF16_SYM) {
     if (!lo) DS_GATHER_LP(__bf16, 2); else DS_GATHER_LP(__bf16, 4);
   } else {
     return hipErrorInvalidValue;

@@ -77,6 +77,7 @@ struct dsgrft_plan_s {
   uint4 *F8;            // e4m3 fragments (K blocks of 64), same 4 planes
   int FBs;              // column blocks of the conjugate-pair table (even)
   uint4 *FS16;          // its fp16 fragments, 2 planes (re, im) x FBs blocks
+  uint4 *FSB16;         // the same columns in bf16, 4 planes (re/im hi, re/im lo)
   int32_t *sym_cols;    // [2][FBs * 32]: fine cell of +d and of -d per
                         //   column (-1: none)
   int32_t *u_off;       // [batch_units][Mp] unit range offsets
@@ -113,7 +114,7 @@ struct dsgrft_plan_s {
     int cap = 0;
     int ng = 0, nf = 0;
     hipEvent_t *ev_g = nullptr, *ev_f = nullptr;  // [2 * cap] each
-    double gbytes = 0.0, fflops = 0.0, fcp = 0.0;
+    double gbytes = 0.0, fflops = 0.0, fcp = 0.0, fxflops = 0.0;
   } prof;
 };
 
@@ -208,8 +209,9 @@ hipError_t launch_noise_power(dsgrft_plan p, const float2 *echo, double *out,
                               hipStream_t s);
 hipError_t launch_detect(dsgrft_plan p, const float *pmax, const int32_t *argf,
                          const int64_t *cells, int64_t cc_begin, int64_t n,
-                         double gamma2, dsgrft_peak *peaks, int32_t cap,
-                         int32_t *count, dsgrft_peak *best, hipStream_t s);
+                         double sigma2, const double *d_sigma2, double ln_pfa,
+                         dsgrft_peak *peaks, int32_t cap, int32_t *count,
+                         dsgrft_peak *best, hipStream_t s);
 hipError_t launch_detect_cfar(dsgrft_plan p, const float *pmax, const int32_t *argf,
                               const int64_t *cells, int64_t cc_begin, int64_t n, int guard,
                               int train, double alpha, dsgrft_peak *peaks, int32_t cap,

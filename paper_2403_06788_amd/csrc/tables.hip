@@ -92,12 +92,14 @@ __global__ void k_fine_tables(int M, int Mp, int C, int Cp, int R, int P, Lat L,
   }
 }
 
-// Conjugate-pair table: column c of block c / 32 holds the fp16 fragments of
-// fine cell cols[c] (zero where cols[c] < 0), copied from the F16 hi planes.
+// Conjugate-pair table: column c of block c / 32 holds the 16-bit fragments
+// of fine cell cols[c] (zero where cols[c] < 0), copied from the first
+// `planes` planes of F16 (fp16: re_hi, im_hi) or FBF16 (bf16: also re_lo,
+// im_lo).
 __global__ void k_sym_table(const uint4 *__restrict__ F16, const int32_t *__restrict__ cols,
-                            int FB, int FBs, int KB, uint4 *__restrict__ FS) {
+                            int FB, int FBs, int KB, int planes, uint4 *__restrict__ FS) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)2 * FBs * KB * 64) return;
+  if (t >= (int64_t)planes * FBs * KB * 64) return;
   const int lane = (int)(t & 63);
   const int64_t q = t >> 6;
   const int kb = (int)(q % KB), cb = (int)((q / KB) % FBs), plane = (int)(q / ((int64_t)KB * FBs));
@@ -166,7 +168,9 @@ hipError_t launch_fine_tables(dsgrft_plan p, hipStream_t s) {
 hipError_t launch_sym_table(dsgrft_plan p, hipStream_t s) {
   const int64_t n = (int64_t)2 * p->FBs * p->KB * 64;
   hipLaunchKernelGGL(k_sym_table, dim3(blocks(n, 256)), dim3(256), 0, s, p->F16,
-                     p->sym_cols, p->FB, p->FBs, p->KB, p->FS16);
+                     p->sym_cols, p->FB, p->FBs, p->KB, 2, p->FS16);
+  hipLaunchKernelGGL(k_sym_table, dim3(blocks(2 * n, 256)), dim3(256), 0, s, p->FBF16,
+                     p->sym_cols, p->FB, p->FBs, p->KB, 4, p->FSB16);
   return hipGetLastError();
 }
 

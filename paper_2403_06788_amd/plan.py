@@ -8,7 +8,6 @@ from __future__ import annotations
 
 import ctypes as C
 
-import numpy as np
 import torch
 
 from . import _lib
@@ -116,7 +115,9 @@ class Plan:
         split 1; "f16", "bf16", "fp8" with split 1-4 products; "f16_3m"
         (three real products per complex product) with split 1; "f16_sym"
         (fine cells in conjugate pairs, four real products per pair) with
-        split 1; "bf16_glo" (the gathered rows split) with split 2."""
+        split 1; "bf16_glo" (the gathered rows split) with split 2;
+        "bf16_sym" over conjugate pairs with split 2 (bf16_glo's products)
+        or 3 (bf16 split 3's products)."""
         echo = _echo(echo)
         if cells is not None:
             cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
@@ -153,29 +154,48 @@ class Plan:
         return (pmax, argf, pw) if full else (pmax, argf)
 
     # ---- detection ----------------------------------------------------------
-    def noise_power(self, echo) -> float:
+    def noise_power(self, echo, as_tensor=False):
+        """Mean |s|^2 of the echo (sigma^2 of eq. (33)): a float, or with
+        as_tensor a one-element float64 CUDA tensor (no synchronisation)."""
         echo = _echo(echo)
         out = torch.empty(1, dtype=torch.float64, device="cuda")
         check("dsgrft_noise_power", self._L.dsgrft_noise_power(
             self._h, _ptr(echo), _ptr(out), _stream()))
-        return float(out.item())
+        return out if as_tensor else float(out.item())
 
-    def detect(self, pmax, argf, gamma2, cap=1024, cells=None, cc_begin=0):
-        """Threshold test on a reduced map.  Returns (peaks structured numpy
-        array [min(count, cap)], count, best peak)."""
-        n = pmax.shape[0]
-        if cells is not None:
-            cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
+    def _detect_out(self, cap):
         peaks = torch.empty((max(cap, 1), PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
         best = torch.empty((1, PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
         count = torch.zeros(1, dtype=torch.int32, device="cuda")
-        check("dsgrft_detect", self._L.dsgrft_detect(
-            self._h, _ptr(pmax), _ptr(argf), _ptr(cells), cc_begin, n, float(gamma2),
-            _ptr(peaks), cap, _ptr(count), _ptr(best), _stream()))
-        cnt = int(count.item())
+        return peaks, best, count
+
+    @staticmethod
+    def _detect_result(fn, status, peaks, best, hc, cap):
+        # E_CAPACITY still delivers the first `cap` entries and the true count
+        if status != 5:
+            check(fn, status)
+        cnt = int(hc.value)
         pk = peaks[:min(cnt, cap)].cpu().numpy().view(PEAK_DTYPE).reshape(-1)
         bp = best.cpu().numpy().view(PEAK_DTYPE).reshape(-1)[0]
         return pk, cnt, bp
+
+    def detect(self, pmax, argf, pfa, sigma2=1.0, cap=1024, cells=None, cc_begin=0):
+        """LRT test (eq. (33)) on a reduced map at false-alarm probability
+        `pfa`; sigma2 is a float or a one-element float64 CUDA tensor (e.g.
+        noise_power(..., as_tensor=True)).  Returns (peaks structured numpy
+        array [min(count, cap)], count, best peak); count > cap means the
+        list was truncated."""
+        n = pmax.shape[0]
+        if cells is not None:
+            cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
+        dev = isinstance(sigma2, torch.Tensor)
+        peaks, best, count = self._detect_out(cap)
+        hc = C.c_int32(0)
+        st = self._L.dsgrft_detect(
+            self._h, _ptr(pmax), _ptr(argf), _ptr(cells), cc_begin, n,
+            0.0 if dev else float(sigma2), _ptr(sigma2) if dev else None, float(pfa),
+            _ptr(peaks), cap, _ptr(count), _ptr(best), C.byref(hc), _stream())
+        return self._detect_result("dsgrft_detect", st, peaks, best, hc, cap)
 
     def detect_cfar(self, pmax, argf, guard, train, alpha, cap=1024, cells=None, cc_begin=0):
         """Cell-averaging CFAR along range on a reduced map.  Returns (peaks
@@ -183,20 +203,19 @@ class Plan:
         n = pmax.shape[0]
         if cells is not None:
             cells = cells.to(device="cuda", dtype=torch.int64).contiguous()
-        peaks = torch.empty((max(cap, 1), PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
-        best = torch.empty((1, PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
-        count = torch.zeros(1, dtype=torch.int32, device="cuda")
-        check("dsgrft_detect_cfar", self._L.dsgrft_detect_cfar(
+        peaks, best, count = self._detect_out(cap)
+        hc = C.c_int32(0)
+        st = self._L.dsgrft_detect_cfar(
             self._h, _ptr(pmax), _ptr(argf), _ptr(cells), cc_begin, n, int(guard), int(train),
-            float(alpha), _ptr(peaks), cap, _ptr(count), _ptr(best), _stream()))
-        cnt = int(count.item())
-        pk = peaks[:min(cnt, cap)].cpu().numpy().view(PEAK_DTYPE).reshape(-1)
-        bp = best.cpu().numpy().view(PEAK_DTYPE).reshape(-1)[0]
-        return pk, cnt, bp
+            float(alpha), _ptr(peaks), cap, _ptr(count), _ptr(best), C.byref(hc), _stream())
+        return self._detect_result("dsgrft_detect_cfar", st, peaks, best, hc, cap)
 
     def threshold(self, sigma2, pfa):
-        """gamma^2 = -M sigma^2 ln P_FA on |Y|^2."""
-        return -self.M * float(sigma2) * float(np.log(pfa))
+        """LRT threshold gamma^2 on |Y|^2 (eq. (33)), from the library."""
+        g = C.c_double()
+        check("dsgrft_lrt_threshold", self._L.dsgrft_lrt_threshold(
+            self._h, float(sigma2), float(pfa), C.byref(g)))
+        return g.value
 
     # ---- measurement -----------------------------------------------------
     def profile_begin(self, capacity=4096):

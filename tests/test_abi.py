@@ -90,7 +90,7 @@ def test_struct_layouts_match_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     mirrors = {"dsgrft_radar": _lib.Radar, "dsgrft_config": _lib.Config,
-               "dsgrft_plan_info": _lib.PlanInfo}
+               "dsgrft_plan_info": _lib.PlanInfo, "dsgrft_profile": _lib.Profile}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dsgrft.h"',
              "int main(void) {"]
     for cname, cls in mirrors.items():
@@ -126,8 +126,12 @@ def test_null_pointers_rejected():
     h = C.c_void_p()
     assert L.dsgrft_plan_create(None, None, C.byref(h)) == 1
     assert L.dsgrft_search(None, 1, 1, None, None, 0, 1, None, None, None) == 1
-    assert L.dsgrft_detect(None, None, None, None, 0, 1, 1.0, None, 0, None, None, None) == 1
-    assert L.dsgrft_detect_cfar(None, None, None, None, 0, 1, 2, 8, 5.0, None, 0, None, None, None) == 1
+    assert L.dsgrft_detect(None, None, None, None, 0, 1, 1.0, None, 1e-6, None, 0, None, None,
+                           None, None) == 1
+    assert L.dsgrft_detect_cfar(None, None, None, None, 0, 1, 2, 8, 5.0, None, 0, None, None,
+                                None, None) == 1
+    g = C.c_double()
+    assert L.dsgrft_lrt_threshold(None, 1.0, 1e-6, C.byref(g)) == 1
     assert L.dsgrft_adjoint_forward(None, None, None, 1, None, None, None) == 1
     info = _lib.PlanInfo()
     assert L.dsgrft_plan_get_info(None, C.byref(info)) == 1

@@ -45,7 +45,8 @@ def test_fd_full_map_fp32_matches_oracle(fcase):
 
 @pytest.mark.parametrize("form,split,tol", [("f32", 1, 1e-5), ("f16", 1, 1e-3),
                                             ("bf16", 3, 1e-4), ("fp8", 3, 1e-2),
-                                            ("f16_3m", 1, 1e-3), ("f16_sym", 1, 1e-3)])
+                                            ("f16_3m", 1, 1e-3), ("f16_sym", 1, 1e-3),
+                                            ("bf16_sym", 3, 1e-4)])
 def test_fd_reduced_map_forms(fcase, form, split, tol):
     pm, af = fcase["plan"].search(fcase["echo_dev"], form, split)
     near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), fcase["P_fd"], tol)

@@ -86,7 +86,8 @@ def test_fp8_against_exact_oracle(case, split):
 
 @pytest.mark.parametrize("form,split", [("f16", 1), ("f16", 2), ("f16", 4), ("bf16", 2),
                                         ("bf16", 4), ("fp8", 1), ("fp8", 3), ("f32", 1),
-                                        ("f16_3m", 1), ("bf16_glo", 2), ("f16_sym", 1)])
+                                        ("f16_3m", 1), ("bf16_glo", 2), ("f16_sym", 1),
+                                        ("bf16_sym", 2), ("bf16_sym", 3)])
 def test_reduced_map_is_max_of_full_map(case, form, split):
     p = case["plan"]
     P = p.search_full(case["echo_dev"], form, split).cpu().numpy()

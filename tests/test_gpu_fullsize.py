@@ -47,12 +47,14 @@ def _check_rows(pm, af, echo, grid, cells, rows, tol):
 
 @pytest.mark.parametrize("form,split,tol", [("f16", 1, 1e-3), ("bf16", 3, 1e-3),
                                             ("f16_3m", 1, 1e-3), ("bf16_glo", 2, 1e-3),
-                                            ("f16_sym", 1, 1e-3)])
+                                            ("f16_sym", 1, 1e-3), ("bf16_sym", 3, 1e-3),
+                                            ("bf16_sym", 2, 1e-3), ("bf16", 2, 1e-3),
+                                            ("fp8", 3, 1e-3), ("fp8", 4, 1e-3)])
 def test_config3_full_search_sampled(form, split, tol):
     case, plan, grid, echo = _setup(3)
     pm, af = plan.search(echo, form, split)
     gamma2 = plan.threshold(1.0, 1e-6)
-    peaks, cnt, best = plan.detect(pm, af, gamma2, cap=4096)
+    peaks, cnt, best = plan.detect(pm, af, 1e-6, 1.0, cap=4096)
     pm, af = pm.cpu().numpy(), af.cpu().numpy()
     assert np.isfinite(pm).all() and (af >= 0).all() and (af < plan.n_fine).all()
     rng = np.random.default_rng(31)

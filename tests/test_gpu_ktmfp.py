@@ -112,7 +112,7 @@ def test_kt_cell_list_matches_range(kcase):
 def test_kt_detect_parameters_match_oracle(kcase):
     p, g = kcase["plan"], kcase["grid"]
     pm, af = p.search(kcase["echo_dev"], "f32fft", 1)
-    _, _, best = p.detect(pm, af, float("inf"))
+    _, _, best = p.detect(pm, af, 1e-300, cap=0)
     k, row, f = int(best["coarse"]), int(best["row"]) - g.n_begin, int(best["fine"])
     assert np.isclose(kcase["P"][k, row, f], kcase["P"].max(), rtol=2 * TOL)
     r0, v, a = KT.peak_params(g, k, row, f)
@@ -133,7 +133,7 @@ def test_kt_folded_target_detected_at_its_cell(q, i1p, i2, r0b):
                       amp=1.0, phase=0.2)
     echo = synth.make_echo(radar, M, c["N"], [tg], 0.0)
     pm, af = p.search(torch.from_numpy(echo).cuda(), "f32fft", 1)
-    _, _, best = p.detect(pm, af, float("inf"))
+    _, _, best = p.detect(pm, af, 1e-300, cap=0)
     qq, i2c = KT.coarse_params(g, KT.lattice(g), int(best["coarse"]))
     f = int(best["fine"])
     assert (qq, f % M - M // 2, i2c + f // M - g.R // 2) == (q, i1p, i2)
@@ -207,7 +207,7 @@ def test_kt_fullsize_folded_target(full3, q, i1p, i2, r0b):
                       amp=1.0, phase=-0.4)
     echo = synth.make_echo(cfg["radar"], M, cfg["N"], [tg], 0.0)
     pm, af = p.search(torch.from_numpy(echo).cuda(), "f32fft", 1)
-    _, _, best = p.detect(pm, af, float("inf"))
+    _, _, best = p.detect(pm, af, 1e-300, cap=0)
     qq, i2c = KT.coarse_params(g, KT.lattice(g), int(best["coarse"]))
     f = int(best["fine"])
     assert (qq, f % M - M // 2, i2c + f // M - g.R // 2) == (q, i1p, i2)
@@ -225,7 +225,7 @@ def test_kt_rejects_what_it_does_not_support():
         Plan(c["fc"], c["fs"], c["prf"], 96, 128, 2, c["axes"], mgift="kt")
     p = _plan(c)
     e = torch.zeros((64, 128), dtype=torch.complex64, device="cuda")
-    for form in ("f32", "f16", "bf16", "fp8", "f16_3m", "f16_sym"):
+    for form in ("f32", "f16", "bf16", "fp8", "f16_3m", "f16_sym", "bf16_sym"):
         with pytest.raises(DsgrftError, match="unsupported"):
             p.search(e, form, 1)
     with pytest.raises(DsgrftError, match="invalid"):

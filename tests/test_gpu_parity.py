@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 TOL = {("f32", 1): 1e-5, ("f16", 1): 1e-3, ("f16", 2): 1e-3, ("f16", 3): 1e-5,
        ("f16", 4): 1e-5, ("bf16", 1): 1e-2, ("bf16", 2): 1e-2, ("bf16", 3): 1e-4,
        ("bf16", 4): 1e-4, ("f16_3m", 1): 1e-3, ("bf16_glo", 2): 1e-2,
-       ("f16_sym", 1): 1e-3}
+       ("f16_sym", 1): 1e-3, ("bf16_sym", 2): 2e-3, ("bf16_sym", 3): 1e-4}
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -97,10 +97,13 @@ def test_detection_matches_oracle(case):
     pm, af = p.search(case["echo_dev"], "f32", 1)
     ref = case["P_ds"]
     pm_o, af_o = OD.reduce_power(ref)
-    # threshold at a level that a handful of cells exceed
-    gamma2 = float(np.quantile(pm_o, 0.995))
+    # threshold at a level that a handful of cells exceed: sigma^2 chosen so
+    # that -M sigma^2 ln(1/2) lands on the map's 99.5% quantile
+    sigma2 = float(np.quantile(pm_o, 0.995)) / (g.M * np.log(2.0))
+    gamma2 = p.threshold(sigma2, 0.5)
+    assert gamma2 == pytest.approx(OD.threshold(g.M, sigma2, 0.5), rel=1e-15)
     tol = 1e-5 * ref.max()
-    peaks, cnt, best = p.detect(pm, af, gamma2, cap=4096)
+    peaks, cnt, best = p.detect(pm, af, 0.5, sigma2, cap=4096)
     assert cnt == len(peaks)
     got = {(int(q["coarse"]), int(q["row"]) - g.n_begin) for q in peaks}
     want = {(k, r) for k, r, _ in OD.detections(pm_o, af_o, gamma2)}
@@ -143,6 +146,9 @@ def test_three_product_form_takes_split_one_only(case):
     for split in (1, 3):
         with pytest.raises(DsgrftError, match="invalid"):
             case["plan"].search(case["echo_dev"], "bf16_glo", split)
+    for split in (1, 4):
+        with pytest.raises(DsgrftError, match="invalid"):
+            case["plan"].search(case["echo_dev"], "bf16_sym", split)
 
 
 def test_row_split_bf16_within_bound(case):
@@ -154,3 +160,16 @@ def test_row_split_bf16_within_bound(case):
     e_g = np.abs(p.search_full(case["echo_dev"], "bf16_glo", 2).cpu().numpy() - ref).max() / ref.max()
     e_f = np.abs(p.search_full(case["echo_dev"], "bf16", 2).cpu().numpy() - ref).max() / ref.max()
     assert e_g <= 1e-2 and e_f <= 1e-2, (e_g, e_f)
+
+
+@pytest.mark.parametrize("split,other", [(2, ("bf16_glo", 2)), (3, ("bf16", 3))])
+def test_bf16_pairs_equal_the_unpaired_form(case, split, other):
+    """The conjugate-pair bf16 form takes the operands and products of the
+    unpaired form with the same split (the -d column is the conjugate of the
+    +d column's rounding), so the two full maps agree up to FP32
+    accumulation order (1e-5 of the peak), on every cell including the ones
+    without a partner."""
+    p = case["plan"]
+    P = p.search_full(case["echo_dev"], "bf16_sym", split).cpu().numpy().astype(np.float64)
+    Q = p.search_full(case["echo_dev"], *other).cpu().numpy().astype(np.float64)
+    assert np.abs(P - Q).max() <= 1e-5 * Q.max()
