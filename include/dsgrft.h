@@ -70,7 +70,13 @@ typedef enum {
  * e4m3(256 F) (lo: e4m3(16 (256 F - hi))), and every (gathered unit, range
  * row) gets the scale 2^(8-e) where 2^(e-1) <= the row's largest |Re|/|Im|
  * echo component < 2^e.  Echo components must stay below 2^100 in
- * magnitude for this form. */
+ * magnitude for this form.
+ * The fp16 forms (F16, F16_3M, F16_SYM) store the gathered rows times 2^sh,
+ * one shift per echo that puts its largest |Re|/|Im| component in
+ * [2^9, 2^10) (clamped to |sh| <= 100), and scale the power back by
+ * 2^(-2 sh); bf16 and FP32 keep FP32's exponent range.  So every form takes
+ * any finite echo whose powers stay inside the FP32 range, and its map
+ * scales exactly with the echo by powers of two. */
 typedef enum {
   DSGRFT_FORM_F32 = 0,   /* plain FP32 (speed baseline), split 1    */
   DSGRFT_FORM_F16 = 1,   /* fp16 x fp16 -> fp32, split 1..4         */

@@ -15,6 +15,7 @@ class DSGRFTObjective(torch.autograd.Function):
     def forward(ctx, plan, echo, theta):
         J, saved = plan.adjoint_forward(echo, theta)
         ctx.plan = plan
+        ctx.theta_device, ctx.theta_dtype = theta.device, theta.dtype
         ctx.save_for_backward(echo, theta.detach().to(torch.float64), saved)
         return J
 
@@ -24,8 +25,9 @@ class DSGRFTObjective(torch.autograd.Function):
         need_echo, need_theta = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         gt, ge = ctx.plan.adjoint_backward(echo, theta, saved, gJ.contiguous(),
                                            want_theta=need_theta, want_echo=need_echo)
-        if gt is not None and ctx.needs_input_grad[2]:
-            gt = gt.to(theta.dtype)
+        if gt is not None:
+            # the gradient goes back on theta's own device and in its dtype
+            gt = gt.to(device=ctx.theta_device, dtype=ctx.theta_dtype)
         return None, ge, gt
 
 

@@ -46,7 +46,7 @@ void release(dsgrft_plan p) {
   if (!p) return;
   void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->FS16, p->FSB16, p->sym_cols, p->u_off, p->u_psi,
                   p->Gbuf[0], p->gscbuf[0], p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
-                  p->kt_spec, p->kt_invd, p->packed, p->det_ws, p->adj_ws};
+                  p->kt_spec, p->kt_invd, p->packed, p->det_ws, p->adj_ws, p->g_shift};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   hipEvent_t evs[] = {p->ev_start, p->ev_g[0], p->ev_g[1], p->ev_f[0], p->ev_f[1]};
@@ -137,6 +137,7 @@ dsgrft_status run_search(dsgrft_plan p, dsgrft_form form, int split,
   DS_TRY(hipStreamWaitEvent(sa, p->ev_start, 0));
   if (p->fd) DS_TRY(launch_range_fft(p, echo, sa));
   if (p->kt) DS_TRY(launch_keystone(p, sa));
+  if (fp16_form(form)) DS_TRY(launch_echo_shift(p, echo, sa));
   const GatherSrc src = gather_src(p, echo);
   int64_t b = 0;
   for (int64_t c0 = 0; c0 < n; c0 += Bc) {
@@ -446,7 +447,8 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
       dalloc((char **)&p->Gbuf[0], 2 * (size_t)bu * per_unit, tot) != hipSuccess ||
       dalloc(&p->packed, (size_t)p->batch_cells * p->rows * 8, tot) != hipSuccess ||
       dalloc((char **)&p->det_ws, p->det_ws_bytes, tot) != hipSuccess ||
-      dalloc(&p->adj_ws, p->adj_ws_bytes, tot) != hipSuccess) {
+      dalloc(&p->adj_ws, p->adj_ws_bytes, tot) != hipSuccess ||
+      dalloc(&p->g_shift, 256, tot) != hipSuccess) {
     (void)hipGetLastError();
     release(p);
     return DSGRFT_E_NOMEM;

@@ -53,6 +53,8 @@
 // (power bits << 32 | ~fine) into the per-(cell, row) result: the largest
 // power wins and equal powers resolve to the smaller fine index, whatever the
 // order of the atomics.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace {
@@ -277,7 +279,7 @@ __device__ inline void mma_step(const Frag<CF::FR> (&a)[CF::NPF][2],
 template <class Op, int SPLIT>
 __global__ __launch_bounds__(256, (Cfg<Op, SPLIT>::MINB)) void k_fine_mfma(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
-    const int32_t *__restrict__ gsc, int fsc,
+    const int32_t *__restrict__ gsc, int fsc, const int32_t *__restrict__ gshift,
     unsigned long long *__restrict__ packed, float *__restrict__ full, int FB,
     int NB, int KS, int rows_p, int64_t nunits, int64_t unit0, int R3, int C,
     int rows, int GN) {
@@ -411,6 +413,8 @@ __global__ __launch_bounds__(256, (Cfg<Op, SPLIT>::MINB)) void k_fine_mfma(
 #undef DS_STEP
 
   // ---- epilogue: |Y|^2, best fine cell per row, merge -----------------
+  // (fp16 rows carry the echo shift 2^sh: the power is scaled by 2^-2sh)
+  const int psh = gshift != nullptr ? -2 * gshift[1] : 0;
   const int64_t ug = unit0 + tm.u;
   const int64_t cpos = ug / R3;
   const unsigned fbase = (unsigned)((ug % R3) * C);
@@ -425,7 +429,7 @@ __global__ __launch_bounds__(256, (Cfg<Op, SPLIT>::MINB)) void k_fine_mfma(
       for (int r = 0; r < 16; ++r) {
         const int f = fb0 + 8 * (r >> 2) + (r & 3);
         const float yr = accR[i][j][r], yi = accI[i][j][r];
-        const float pw = yr * yr + yi * yi;
+        const float pw = ldexpf(yr * yr + yi * yi, psh);
         if (f < C) {
           const unsigned ff = fbase + (unsigned)f;
           const unsigned long long key =
@@ -464,7 +468,7 @@ __device__ inline uint4 add_h8(uint4 a, uint4 b) {
 }
 
 __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
-    const uint4 *__restrict__ F, const uint4 *__restrict__ G,
+    const uint4 *__restrict__ F, const uint4 *__restrict__ G, const int32_t *__restrict__ gshift,
     unsigned long long *__restrict__ packed, float *__restrict__ full, int FB,
     int NB, int KS, int64_t nunits, int64_t unit0, int R3, int C, int rows, int GN) {
   constexpr int NST = 4, NBG = 4;
@@ -573,6 +577,7 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
   }
 
   // ---- epilogue as in k_fine_mfma ----------------------------------------
+  const int psh = -2 * gshift[1];
   const int64_t ug = unit0 + tm.u;
   const int64_t cpos = ug / R3;
   const unsigned fbase = (unsigned)((ug % R3) * C);
@@ -588,7 +593,7 @@ __global__ __launch_bounds__(256, 2) void k_fine_mfma3(
         const int f = fb0 + 8 * (r >> 2) + (r & 3);
         const float p1 = acc[0][i][j][r], p2 = acc[1][i][j][r], p3 = acc[2][i][j][r];
         const float yr = p1 - p2, yi = p3 - p1 - p2;
-        const float pw = yr * yr + yi * yi;
+        const float pw = ldexpf(yr * yr + yi * yi, psh);
         if (f < C) {
           const unsigned ff = fbase + (unsigned)f;
           const unsigned long long key =
@@ -653,9 +658,9 @@ struct SymCfg {
 template <class Op, int NPF, int NPG>
 __global__ __launch_bounds__(256, (SymCfg<NPF, NPG>::WG)) void k_fine_mfma_sym(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
-    const int32_t *__restrict__ cols, unsigned long long *__restrict__ packed,
-    float *__restrict__ full, int FBs, int NB, int KS, int64_t nunits, int64_t unit0,
-    int R3, int C, int rows, int GN) {
+    const int32_t *__restrict__ cols, const int32_t *__restrict__ gshift,
+    unsigned long long *__restrict__ packed, float *__restrict__ full, int FBs, int NB,
+    int KS, int64_t nunits, int64_t unit0, int R3, int C, int rows, int GN) {
   using SC = SymCfg<NPF, NPG>;
   constexpr int NST = SC::NST, CH = SC::CH, CPT = SC::CPT;
   constexpr int NBG = 4, NFB = 2;  // row / column blocks per tile
@@ -767,6 +772,7 @@ __global__ __launch_bounds__(256, (SymCfg<NPF, NPG>::WG)) void k_fine_mfma_sym(
   }
 
   // ---- epilogue: both cells of each column ---------------------------------
+  const int psh = gshift != nullptr ? -2 * gshift[1] : 0;
   const int64_t ug = unit0 + tm.u;
   const int64_t cpos = ug / R3;
   const unsigned fbase = (unsigned)((ug % R3) * C);
@@ -784,7 +790,7 @@ __global__ __launch_bounds__(256, (SymCfg<NPF, NPG>::WG)) void k_fine_mfma_sym(
       const float pri = acc[2][j][r], pir = acc[3][j][r];
       const float ar = prr - pii, ai = pri + pir;  // +d
       const float br = prr + pii, bi = pri - pir;  // -d
-      const float pa = ar * ar + ai * ai, pb = br * br + bi * bi;
+      const float pa = ldexpf(ar * ar + ai * ai, psh), pb = ldexpf(br * br + bi * bi, psh);
       if (fp >= 0) {
         const unsigned ff = fbase + (unsigned)fp;
         best[j] = umax64(best[j], ((unsigned long long)__float_as_uint(pa) << 32) | (0xffffffffu - ff));
@@ -825,8 +831,9 @@ hipError_t launch_t(dsgrft_plan p, const void *F, int fsc, int64_t nunits,
   using CF = Cfg<Op, SPLIT>;
   int64_t tiles = nunits * (p->NB / CF::NBG) * (p->FB / 4);
   const int32_t *gsc = Op::FR == 2 ? p->g_scale : nullptr;
+  const int32_t *gsh = std::is_same<Op, OpF16>::value ? p->g_shift : nullptr;
   hipLaunchKernelGGL((k_fine_mfma<Op, SPLIT>), dim3((unsigned)tiles), dim3(256), 0, s,
-                     (const uint4 *)F, (const uint4 *)p->G, gsc, fsc, p->packed, full,
+                     (const uint4 *)F, (const uint4 *)p->G, gsc, fsc, gsh, p->packed, full,
                      p->FB, p->NB, p->Mp / Op::KSTEP, p->rows_p, nunits, unit0, p->R3,
                      p->C, p->rows, 8);
   return hipGetLastError();
@@ -871,7 +878,8 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
       if (split != 1 || (p->Mp / OpF16::KSTEP) % 2 != 0) return hipErrorInvalidValue;
       const int64_t tiles = nunits * (p->NB / 4) * (p->FB / 4);
       hipLaunchKernelGGL(k_fine_mfma3, dim3((unsigned)tiles), dim3(256), 0, s,
-                         (const uint4 *)p->F16, (const uint4 *)p->G, p->packed, full, p->FB,
+                         (const uint4 *)p->F16, (const uint4 *)p->G, p->g_shift, p->packed,
+                         full, p->FB,
                          p->NB, p->Mp / OpF16::KSTEP, nunits, unit0, p->R3, p->C, p->rows, 8);
       return hipGetLastError();
     }
@@ -882,16 +890,17 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
           p->FBs <= 0 || p->FBs % 2 != 0 || p->NB % 4 != 0)
         return hipErrorInvalidValue;
       const int64_t tiles = nunits * (p->NB / 4) * (p->FBs / 2);
-#define DS_SYM(OP, NPF, NPG, TAB)                                                       \
+#define DS_SYM(OP, NPF, NPG, TAB, SH)                                                   \
   hipLaunchKernelGGL((k_fine_mfma_sym<OP, NPF, NPG>), dim3((unsigned)tiles), dim3(256), 0, s, \
-                     (const uint4 *)(TAB), (const uint4 *)p->G, p->sym_cols, p->packed, full, \
-                     p->FBs, p->NB, p->Mp / OP::KSTEP, nunits, unit0, p->R3, p->C, p->rows, 4)
+                     (const uint4 *)(TAB), (const uint4 *)p->G, p->sym_cols, SH, p->packed,  \
+                     full, p->FBs, p->NB, p->Mp / OP::KSTEP, nunits, unit0, p->R3, p->C,     \
+                     p->rows, 4)
       if (!b)
-        DS_SYM(OpF16, 2, 2, p->FS16);
+        DS_SYM(OpF16, 2, 2, p->FS16, p->g_shift);
       else if (split == 2)
-        DS_SYM(OpBF16, 2, 4, p->FSB16);
+        DS_SYM(OpBF16, 2, 4, p->FSB16, nullptr);
       else
-        DS_SYM(OpBF16, 4, 4, p->FSB16);
+        DS_SYM(OpBF16, 4, 4, p->FSB16, nullptr);
 #undef DS_SYM
       return hipGetLastError();
     }

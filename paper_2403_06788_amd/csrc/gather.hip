@@ -13,6 +13,14 @@
 //    (Mp/16) pulse blocks x 64 lanes x 8 elements; lane l holds row
 //    32 nb + l % 32 and pulses 16 kb + 8 (l / 32) + e.  A wave writes whole
 //    1 KiB fragments per plane, contiguously.
+//    The fp16 forms store G 2^sh with one shift per echo: with mx the
+//    echo's largest |Re| or |Im| component and 2^(e-1) <= mx < 2^e,
+//    sh = 10 - e (0 for an all-zero echo, clamped to [-100, 100]), so the
+//    largest component sits in [2^9, 2^10) whatever the echo's scale: far
+//    from fp16's overflow (65504) even after the de-ramp rotation, the
+//    three-product form's operand sums and the frequency-domain shift's
+//    interpolation overshoot, and 2^24 above its subnormal range.  The fine
+//    search scales the power back by 2^(-2 sh) (exact).
 //  * 8-bit form: B-operand fragments of v_mfma_scale_f32_32x32x64_f8f6f4
 //    (OCP e4m3), K blocks of 64 pulses, 2 KiB each as two halves
 //    [e / 16][lane][e % 16], lane l holding row 32 nb + l % 32 and pulses
@@ -75,6 +83,34 @@ __device__ inline uint16_t b16(T x) {
   return __builtin_bit_cast(uint16_t, x);
 }
 
+// Echo scale of the fp16 forms: sh[0] = bits of the largest |Re|/|Im|
+// component (non-negative floats order as their bit patterns), sh[1] =
+// 10 - e with 2^(e-1) <= max < 2^e.
+__global__ void k_shift_zero(int32_t *__restrict__ sh) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sh[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_echo_maxabs(const float2 *__restrict__ e, int64_t n,
+                                                     int32_t *__restrict__ sh) {
+  float mx = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    const float2 v = e[i];
+    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  if ((threadIdx.x & 63) == 0) atomicMax((unsigned *)sh, __float_as_uint(mx));
+}
+
+__global__ void k_shift_final(int32_t *__restrict__ sh) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const float mx = __uint_as_float((unsigned)sh[0]);
+  int e = 0;
+  if (mx > 0.f) (void)frexpf(mx, &e);
+  const int s = 10 - e;
+  sh[1] = s < -100 ? -100 : (s > 100 ? 100 : s);
+}
+
 // One workgroup per (unit, row block of 32 rows, 4 KPW pulse blocks): the
 // offsets and de-ramp phasors of its 64 KPW pulses are staged in LDS, then
 // wave w writes the fragments of pulse blocks kb0 + w KPW .. + KPW - 1, so
@@ -85,7 +121,8 @@ template <typename T, int NP>
 __global__ __launch_bounds__(256) void k_gather_lp(
     const float2 *__restrict__ echo, const int32_t *__restrict__ off,
     const float2 *__restrict__ psi, int M, int N, int Mp, int rows, int n_begin,
-    int64_t estride, int NB, int KB, int64_t nunits, uint4 *__restrict__ G) {
+    int64_t estride, int NB, int KB, int64_t nunits, const int32_t *__restrict__ shift,
+    uint4 *__restrict__ G) {
   constexpr int PW = 4 * KPW * 16;  // pulses per workgroup
   __shared__ int32_t s_off[PW];
   __shared__ float2 s_psi[PW];
@@ -104,6 +141,7 @@ __global__ __launch_bounds__(256) void k_gather_lp(
   echo += u * estride;
   const int r = nb * 32 + (lane & 31);
   const int64_t plane = (int64_t)NB * KB * 64;
+  const float sc = shift != nullptr ? ldexpf(1.0f, shift[1]) : 1.0f;
   auto pack = [](const uint16_t *h) {
     return make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
                       h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
@@ -119,6 +157,8 @@ __global__ __launch_bounds__(256) void k_gather_lp(
       float2 v = make_float2(0.f, 0.f);
       if (kb < KB && m < M && r < rows)
         v = cmul(sample(echo, N, m, n_begin + r + s_off[ml]), s_psi[ml]);
+      v.x *= sc;
+      v.y *= sc;
       T hr = (T)v.x, hi = (T)v.y;
       re_h[e] = b16(hr);
       im_h[e] = b16(hi);
@@ -288,6 +328,15 @@ hipError_t launch_mgift_out(dsgrft_plan p, GatherSrc src, int64_t nunits,
   return hipGetLastError();
 }
 
+hipError_t launch_echo_shift(dsgrft_plan p, const float2 *echo, hipStream_t s) {
+  const int64_t n = (int64_t)p->M * p->N;
+  const int64_t nb = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
+  hipLaunchKernelGGL(k_shift_zero, dim3(1), dim3(64), 0, s, p->g_shift);
+  hipLaunchKernelGGL(k_echo_maxabs, dim3((unsigned)nb), dim3(256), 0, s, echo, n, p->g_shift);
+  hipLaunchKernelGGL(k_shift_final, dim3(1), dim3(64), 0, s, p->g_shift);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
                             GatherSrc src, int64_t nunits, hipStream_t s) {
   // G's lo planes enter from split 3 on (split 2 adds the fine table's lo)
@@ -312,15 +361,15 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
   }
   const int64_t kg = (p->KB + 4 * KPW - 1) / (4 * KPW);
   dim3 grid((unsigned)(nunits * p->NB * kg));
-#define DS_GATHER_LP(T, NP)                                                           \
+#define DS_GATHER_LP(T, NP, SH)                                                       \
   hipLaunchKernelGGL((k_gather_lp<T, NP>), grid, dim3(256), 0, s, src.echo, p->u_off,   \
                      p->u_psi, p->M, src.N, p->Mp, p->rows, src.n_begin,                \
-                     src.unit_stride, p->NB, p->KB, nunits, G)
-  if (form == DSGRFT_FORM_F16 || form == DSGRFT_FORM_F16_3M || form == DSGRFT_FORM_F16_SYM) {
-    if (!lo) DS_GATHER_LP(_Float16, 2); else DS_GATHER_LP(_Float16, 4);
+                     src.unit_stride, p->NB, p->KB, nunits, SH, G)
+  if (fp16_form(form)) {
+    if (!lo) DS_GATHER_LP(_Float16, 2, p->g_shift); else DS_GATHER_LP(_Float16, 4, p->g_shift);
   } else if (form == DSGRFT_FORM_BF16 || form == DSGRFT_FORM_BF16_GLO ||
              form == DSGRFT_FORM_BF16_SYM) {
-    if (!lo) DS_GATHER_LP(__bf16, 2); else DS_GATHER_LP(__bf16, 4);
+    if (!lo) DS_GATHER_LP(__bf16, 2, nullptr); else DS_GATHER_LP(__bf16, 4, nullptr);
   } else {
     return hipErrorInvalidValue;
   }

@@ -85,6 +85,8 @@ struct dsgrft_plan_s {
   void *G;              // gathered batch being produced or consumed (a slot
                         //   of Gbuf), max 8 bytes per (unit,row,pulse)
   int32_t *g_scale;     // [batch_units][rows_p] per-row E8M0 codes of that slot
+  int32_t *g_shift;     // [2]: largest |Re|/|Im| echo component (float bits)
+                        //   and the fp16 forms' power-of-two shift of G
   void *Gbuf[2];        // two slots: batch b + 1 is gathered while the fine
   int32_t *gscbuf[2];   //   search reads batch b
   hipStream_t aux;      // producer stream of the search pipeline (tables,
@@ -169,6 +171,11 @@ hipError_t launch_coarse_tables(dsgrft_plan p, int64_t cc_begin, int64_t n,
 size_t detect_ws_bytes(int64_t max_entries);
 // Where the gathers read: the echo ([M][N], window from n_begin) or, in the
 // frequency-domain mode, the shifted rows of each unit ([u][M][rows_p]).
+// Forms whose gathered rows are fp16 (scaled by the echo shift).
+inline bool fp16_form(dsgrft_form f) {
+  return f == DSGRFT_FORM_F16 || f == DSGRFT_FORM_F16_3M || f == DSGRFT_FORM_F16_SYM;
+}
+
 struct GatherSrc {
   const float2 *echo;
   int N, n_begin;
@@ -177,6 +184,7 @@ struct GatherSrc {
 GatherSrc gather_src(dsgrft_plan p, const float2 *echo);
 hipError_t launch_gather_f32(dsgrft_plan p, GatherSrc src, int64_t nunits,
                              hipStream_t s);
+hipError_t launch_echo_shift(dsgrft_plan p, const float2 *echo, hipStream_t s);
 hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
                             GatherSrc src, int64_t nunits, hipStream_t s);
 hipError_t launch_mgift_out(dsgrft_plan p, GatherSrc src, int64_t nunits,

@@ -109,3 +109,21 @@ def test_refine_increases_objective(p2):
     assert np.all(J >= J0 * (1 - 1e-12))
     Jc, _ = plan.adjoint_forward(p2["echo_dev"], th)
     np.testing.assert_allclose(Jc.cpu().numpy(), J, rtol=1e-12)
+
+
+def test_autograd_cpu_float32_theta(p2):
+    """theta on the CPU in float32 with requires_grad: the gradient comes back
+    on the CPU in float32 (and equals the FP64 gradient of the same points)."""
+    from paper_2403_06788_amd.autograd import objective
+    plan = p2["plan"]
+    th0 = _thetas(p2, 4, 8).astype(np.float32)
+    theta = torch.tensor(th0, dtype=torch.float32, requires_grad=True)
+    J = objective(plan, p2["echo_dev"], theta)
+    J.sum().backward()
+    assert theta.grad.device.type == "cpu" and theta.grad.dtype == torch.float32
+    th64 = torch.from_numpy(th0.astype(np.float64))
+    J64, saved = plan.adjoint_forward(p2["echo_dev"], th64)
+    gt, _ = plan.adjoint_backward(p2["echo_dev"], th64, saved,
+                                  torch.ones(4, dtype=torch.float64), want_echo=False)
+    np.testing.assert_allclose(theta.grad.numpy(), gt.cpu().numpy().astype(np.float32),
+                               rtol=1e-6)
