@@ -282,6 +282,23 @@ dsgrft_status dsgrft_grft(dsgrft_plan plan, const void *d_echo,
 dsgrft_status dsgrft_noise_power(dsgrft_plan plan, const void *d_echo,
                                  double *d_sigma2, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc), who
+ * therefore cannot create a plan there either: dsgrft_noise_power without a
+ * plan.  Same kernels, same summation order and so the same double as
+ * dsgrft_noise_power on the same echo [M][N] (complex64, device); writes one
+ * double to d_sigma2.  The partial sums (one per 65536 samples) live in a
+ * static device array of DSGRFT_NOALLOC_MAX_PARTS doubles that each GPU the
+ * library runs on holds until the process ends; M N above
+ * 65536 * DSGRFT_NOALLOC_MAX_PARTS (2^28 samples) returns E_INVALID, as do
+ * NULL pointers and M or N < 1.  Allocates nothing and does not
+ * synchronise.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or threads) race; order them on one
+ * stream. */
+#define DSGRFT_NOALLOC_MAX_PARTS 4096
+dsgrft_status dsgrft_noise_power_noalloc(const void *d_echo, int32_t M, int32_t N,
+                                         double *d_sigma2, void *stream);
+
 /* LRT threshold on |Y|^2 (Sec. III-C, eqs. (31), (33)): gamma^2 =
  * -M sigma^2 ln P_FA, evaluated in FP64 as (-M sigma^2) ln P_FA, the K
  * frequency bins of eq. (33) folded into sigma^2 (see dsgrft_noise_power).

@@ -88,6 +88,7 @@ def lib():
         "dsgrft_grft": [vp, vp, i64, i64, vp, vp, vp, vp],
         "dsgrft_noise_power": [vp, vp, vp, vp],
         "dsgrft_lrt_threshold": [vp, dbl, dbl, C.POINTER(dbl)],
+        "dsgrft_noise_power_noalloc": [vp, i32, i32, vp, vp],
         "dsgrft_detect": [vp, vp, vp, vp, i64, i64, dbl, vp, dbl, vp, i32, vp, vp,
                           C.POINTER(i32), vp],
         "dsgrft_detect_cfar": [vp, vp, vp, vp, i64, i64, i32, i32, dbl, vp, i32, vp, vp,
@@ -120,7 +121,8 @@ def exported_symbols():
     return ["dsgrft_plan_create", "dsgrft_plan_destroy", "dsgrft_plan_get_info",
             "dsgrft_status_string", "dsgrft_coarse_tables", "dsgrft_mgift",
             "dsgrft_search", "dsgrft_search_full", "dsgrft_grft",
-            "dsgrft_noise_power", "dsgrft_lrt_threshold", "dsgrft_detect",
+            "dsgrft_noise_power", "dsgrft_noise_power_noalloc", "dsgrft_lrt_threshold",
+            "dsgrft_detect",
             "dsgrft_detect_cfar",
             "dsgrft_adjoint_forward",
             "dsgrft_adjoint_backward", "dsgrft_refine",

@@ -16,6 +16,8 @@
 // chunk maxima, one exclusive scan (and the global maximum, smallest flat
 // index on ties), then an ordered write per chunk.  A chunk is 4096 map
 // entries; thread t of a chunk owns entries t, t + 256, ... .
+#include <mutex>
+
 #include "internal.h"
 
 namespace {
@@ -326,4 +328,54 @@ hipError_t launch_noise_power(dsgrft_plan p, const float2 *echo, double *out,
                      part);
   hipLaunchKernelGGL(k_noise_final, dim3(1), dim3(64), 0, s, part, nb, n, out);
   return hipGetLastError();
+}
+
+// ---- plan-free noise power that allocates nothing --------------------------
+//
+// The partial sums of dsgrft_noise_power_noalloc live in `scratch`, a static
+// device array of DSGRFT_NOALLOC_MAX_PARTS doubles (one per 65536 echo
+// samples; each GPU holds its own copy until the process ends).  Host code
+// must not pass `scratch` itself to a kernel (on the host it names a
+// host-side stand-in): the device address is looked up once per device with
+// hipGetSymbolAddress, with that device current, and cached.  The partial
+// kernel writes every entry the final kernel reads, so nothing needs
+// clearing between calls; calls that overlap on one GPU race on the array.
+static __device__ __align__(256) double scratch[DSGRFT_NOALLOC_MAX_PARTS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_for_device(int dev, double **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" dsgrft_status dsgrft_noise_power_noalloc(const void *d_echo, int32_t M, int32_t N,
+                                                    double *d_sigma2, void *stream) {
+  if (!d_echo || !d_sigma2 || M < 1 || N < 1) return DSGRFT_E_INVALID;
+  const int64_t n = (int64_t)M * N;
+  const int64_t nb = (n + 65535) / 65536;
+  if (nb > DSGRFT_NOALLOC_MAX_PARTS) return DSGRFT_E_INVALID;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return DSGRFT_E_DEVICE;
+  if (dev < 0 || dev >= kMaxDevices) return DSGRFT_E_UNSUPPORTED;
+  double *part = nullptr;
+  if (scratch_for_device(dev, &part) != hipSuccess) return DSGRFT_E_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_noise_partial, dim3((unsigned)nb), dim3(TPB), 0, s,
+                     (const float2 *)d_echo, n, part);
+  hipLaunchKernelGGL(k_noise_final, dim3(1), dim3(64), 0, s, part, nb, n, d_sigma2);
+  return hipGetLastError() == hipSuccess ? DSGRFT_OK : DSGRFT_E_DEVICE;
 }

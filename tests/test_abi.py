@@ -132,6 +132,11 @@ def test_null_pointers_rejected():
                                 None, None) == 1
     g = C.c_double()
     assert L.dsgrft_lrt_threshold(None, 1.0, 1e-6, C.byref(g)) == 1
+    # the no-allocation noise power checks its arguments before any HIP call
+    fake = C.c_void_p(256)
+    assert L.dsgrft_noise_power_noalloc(None, 4, 4, fake, None) == 1
+    assert L.dsgrft_noise_power_noalloc(fake, 0, 4, fake, None) == 1
+    assert L.dsgrft_noise_power_noalloc(fake, 1 << 15, 1 << 14, fake, None) == 1  # > 2^28
     assert L.dsgrft_adjoint_forward(None, None, None, 1, None, None, None) == 1
     info = _lib.PlanInfo()
     assert L.dsgrft_plan_get_info(None, C.byref(info)) == 1
