@@ -25,6 +25,7 @@ import torch
 
 import synth
 from oracle import detect as OD
+from oracle import transforms as OT
 from oracle.grid import Axis, Radar, make_grid
 
 pytestmark = pytest.mark.gpu
@@ -74,18 +75,13 @@ def _fine_ok(entry, f_dev, band):
     return f_dev == f if not ties else f_dev in ties | {f}
 
 
-@pytest.mark.parametrize("cfg,form,split,tol",
-                         [(c, f, s, t) for c in (2, 3) for f, s, t in FORMS[c]])
-def test_detections_match_oracle(cfg, form, split, tol):
-    gold, plan, grid, echo = _setup(cfg)
-    print(f"config {cfg} {form} x{split}", flush=True)
-    pm, af = plan.search(echo, form, split)
-    scale = gold["pmax"]
+def _compare(plan, grid, pm, af, ents, top, scale, pfas, sigma2, tol, gammas=None):
     band = 2 * tol * scale
-    ents = {(e[0], e[1]): e for e in gold["entries"]}
-    for pfa, g2 in zip(gold["pfa"], gold["gamma2"]):
-        assert plan.threshold(gold["sigma2"], pfa) == g2
-        peaks, cnt, best = plan.detect(pm, af, pfa, gold["sigma2"], cap=1 << 16)
+    for i, pfa in enumerate(pfas):
+        g2 = plan.threshold(sigma2, pfa)
+        if gammas is not None:
+            assert g2 == gammas[i]
+        peaks, cnt, best = plan.detect(pm, af, pfa, sigma2, cap=1 << 16)
         assert cnt == len(peaks)
         got = {(int(q["coarse"]), int(q["row"])): q for q in peaks}
         keys = [(int(q["coarse"]), int(q["row"])) for q in peaks]
@@ -103,10 +99,60 @@ def test_detections_match_oracle(cfg, form, split, tol):
             assert (q["r0"], q["v"], q["a"], q["j"]) == pytest.approx((r0, v, a, j), rel=1e-15,
                                                                       abs=1e-12)
     # global maximum
-    top = gold["top"]
     cand = {(t[0], t[1]) for t in top if t[3] >= top[0][3] - band}
     kb = (int(best["coarse"]), int(best["row"]))
     assert kb in cand, (kb, top[:3])
     assert abs(float(best["power"]) - top[0][3]) <= tol * scale
     if kb in ents:
         assert _fine_ok(ents[kb], int(best["fine"]), band)
+    return len(got)
+
+
+@pytest.mark.parametrize("cfg,form,split,tol",
+                         [(c, f, s, t) for c in (2, 3) for f, s, t in FORMS[c]])
+def test_detections_match_oracle(cfg, form, split, tol):
+    gold, plan, grid, echo = _setup(cfg)
+    print(f"config {cfg} {form} x{split}", flush=True)
+    pm, af = plan.search(echo, form, split)
+    ents = {(e[0], e[1]): e for e in gold["entries"]}
+    _compare(plan, grid, pm, af, ents, gold["top"], gold["pmax"], gold["pfa"], gold["sigma2"],
+             tol, gold["gamma2"])
+
+
+@pytest.fixture(scope="module")
+def config1():
+    """The M = 64 workload: its whole oracle map is computed here (3 coarse
+    cells x 256 rows x 100 fine cells), so every reduced entry is known."""
+    from paper_2403_06788_amd.plan import Plan
+    c = synth.CONFIGS[1]
+    r = c["radar"]
+    grid = make_grid(Radar(r.fc, r.fs, r.prf), c["M"], c["N"], c["order"],
+                     [Axis(*a) for a in c["axes"]])
+    e = synth.config_case(1)["echo"]
+    P = OT.dsgrft_power(e.astype(np.complex128), grid)
+    pm, af = OD.reduce_power(P)
+    ents = {}
+    for k in range(P.shape[0]):
+        for n in range(P.shape[1]):
+            near = np.nonzero(P[k, n] >= 0.99 * pm[k, n])[0]
+            ents[(k, n)] = [k, n, int(af[k, n]), float(pm[k, n]),
+                            [[int(f), float(P[k, n, f])] for f in near if f != af[k, n]]]
+    order = sorted(ents.values(), key=lambda x: -x[3])
+    top = [[x[0], x[1], x[2], x[3]] for x in order[:64]]
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"])
+    return dict(plan=plan, grid=grid, echo=torch.from_numpy(e).cuda(), ents=ents, top=top,
+                scale=float(P.max()))
+
+
+@pytest.mark.parametrize("form,split,tol", [("f32", 1, 1e-5), ("f32fft", 1, 1e-5),
+                                            ("f16_sym", 1, 1e-3), ("f16_3m", 1, 1e-3),
+                                            ("f16", 1, 1e-3), ("bf16_sym", 3, 1e-3),
+                                            ("bf16", 3, 1e-3), ("fp8", 3, 1e-2)])
+def test_config1_every_entry(config1, form, split, tol):
+    """LRT detections of the M = 64 workload at P_FA 1e-9 ... 1e-1 (from the
+    target alone to a third of the map) against the complete oracle map."""
+    c = config1
+    pm, af = c["plan"].search(c["echo"], form, split)
+    n = [_compare(c["plan"], c["grid"], pm, af, c["ents"], c["top"], c["scale"], [pfa], 1.0, tol)
+         for pfa in (1e-9, 1e-6, 1e-3, 1e-2, 1e-1)]
+    assert n[-1] > 100 and n[0] >= 1
