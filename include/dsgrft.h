@@ -409,6 +409,21 @@ typedef struct {
 dsgrft_status dsgrft_profile_begin(dsgrft_plan plan, int32_t capacity);
 dsgrft_status dsgrft_profile_end(dsgrft_plan plan, dsgrft_profile *out);
 
+/* Attainable matrix-core rate, for the roofline (a measurement aid, not part
+ * of the method).  Under sustained matrix work on random data the chip runs
+ * at a power-limited clock, below the one the published peak assumes.  This
+ * runs a register-only loop of v_mfma_f32_32x32x16_f16 (form
+ * DSGRFT_FORM_F16) or _bf16 (DSGRFT_FORM_BF16) on random operands (random
+ * signs, mantissas and exponents in [2^-8, 2^1); each MFMA takes another
+ * operand pair; no memory traffic) on the current device, for about `ms`
+ * milliseconds after a warm-up, on the default stream, and waits for it.
+ * *h_tflops receives the executed rate (32768 flops per MFMA) and *h_ghz
+ * the mean shader clock the workgroups read while it ran.  Allocates two
+ * small device buffers for its results (it is not an execution entry
+ * point).  E_INVALID for another form, NULL outputs or ms outside
+ * [1, 10000]. */
+dsgrft_status dsgrft_mfma_probe(dsgrft_form form, double ms, double *h_tflops, double *h_ghz);
+
 #ifdef __cplusplus
 }
 #endif

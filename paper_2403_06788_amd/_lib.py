@@ -98,6 +98,7 @@ def lib():
         "dsgrft_refine": [vp, vp, vp, i32, i32, vp, vp],
         "dsgrft_profile_begin": [vp, i32],
         "dsgrft_profile_end": [vp, C.POINTER(Profile)],
+        "dsgrft_mfma_probe": [C.c_int, dbl, C.POINTER(dbl), C.POINTER(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -126,4 +127,4 @@ def exported_symbols():
             "dsgrft_detect_cfar",
             "dsgrft_adjoint_forward",
             "dsgrft_adjoint_backward", "dsgrft_refine",
-            "dsgrft_profile_begin", "dsgrft_profile_end"]
+            "dsgrft_profile_begin", "dsgrft_profile_end", "dsgrft_mfma_probe"]

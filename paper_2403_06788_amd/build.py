@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdsgrft.so")
 
 SOURCES = ["capi.cpp", "tables.hip", "gather.hip", "fine_mfma.hip",
-           "fine_plain.hip", "fine_fft.hip", "mgift_fd.hip", "ktmfp.hip", "grft.hip", "detect.hip", "adjoint.hip"]
+           "fine_plain.hip", "fine_fft.hip", "mgift_fd.hip", "ktmfp.hip", "grft.hip", "detect.hip", "adjoint.hip",
+           "probe.hip"]
 
 # Packed FP32 instructions are disabled: hand-written code must not rely on
 # them and the compiler must not form them.

@@ -226,6 +226,14 @@ class Plan:
         check("dsgrft_profile_end", self._L.dsgrft_profile_end(self._h, C.byref(pr)))
         return {k: getattr(pr, k) for k, _ in pr._fields_}
 
+    @staticmethod
+    def mfma_probe(form="f16", ms=50.0):
+        """Attainable matrix-core rate on random operands: (TFLOP/s, GHz)."""
+        t, g = C.c_double(), C.c_double()
+        check("dsgrft_mfma_probe", _lib.lib().dsgrft_mfma_probe(FORMS[form], float(ms),
+                                                                C.byref(t), C.byref(g)))
+        return t.value, g.value
+
     # ---- adjoint --------------------------------------------------------------
     def adjoint_forward(self, echo, theta):
         echo = _echo(echo)

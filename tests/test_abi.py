@@ -132,6 +132,11 @@ def test_null_pointers_rejected():
                                 None, None) == 1
     g = C.c_double()
     assert L.dsgrft_lrt_threshold(None, 1.0, 1e-6, C.byref(g)) == 1
+    # the MFMA probe checks its arguments before any HIP call
+    t, gh = C.c_double(), C.c_double()
+    assert L.dsgrft_mfma_probe(0, 10.0, C.byref(t), C.byref(gh)) == 1        # FP32: no
+    assert L.dsgrft_mfma_probe(1, 0.0, C.byref(t), C.byref(gh)) == 1         # ms < 1
+    assert L.dsgrft_mfma_probe(1, 10.0, None, C.byref(gh)) == 1
     # the no-allocation noise power checks its arguments before any HIP call
     fake = C.c_void_p(256)
     assert L.dsgrft_noise_power_noalloc(None, 4, 4, fake, None) == 1
