@@ -77,6 +77,7 @@ def _fine_ok(entry, f_dev, band):
 
 def _compare(plan, grid, pm, af, ents, top, scale, pfas, sigma2, tol, gammas=None):
     band = 2 * tol * scale
+    worst = 0.0
     for i, pfa in enumerate(pfas):
         g2 = plan.threshold(sigma2, pfa)
         if gammas is not None:
@@ -93,6 +94,7 @@ def _compare(plan, grid, pm, af, ents, top, scale, pfas, sigma2, tol, gammas=Non
         assert set(got) <= set(ents), sorted(set(got) - set(ents))[:10]
         for k, q in got.items():
             e = ents[k]
+            worst = max(worst, abs(float(q["power"]) - e[3]) / scale)
             assert abs(float(q["power"]) - e[3]) <= tol * scale, (k, float(q["power"]), e[3])
             assert _fine_ok(e, int(q["fine"]), band), (k, int(q["fine"]), e[2], e[4])
             r0, v, a, j = OD.peak_params(grid, k[0], k[1], int(q["fine"]))
@@ -105,6 +107,7 @@ def _compare(plan, grid, pm, af, ents, top, scale, pfas, sigma2, tol, gammas=Non
     assert abs(float(best["power"]) - top[0][3]) <= tol * scale
     if kb in ents:
         assert _fine_ok(ents[kb], int(best["fine"]), band)
+    print(f"largest power error on the detections: {worst:.3e} of the peak", flush=True)
     return len(got)
 
 
