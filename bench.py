@@ -710,7 +710,8 @@ def bench_jerk(args):
     n = cells.numel()
     cp = float(n) * plan.rows * plan.n_fine * plan.M
     res = {}
-    for form, split in (("f16_sym", 1), ("f16_3m", 1), ("f16", 1), ("bf16", 1), ("bf16", 3)):
+    for form, split in (("f16_sym", 1), ("bf16_sym", 3), ("bf16_sym", 2), ("f16_3m", 1),
+                        ("f16", 1), ("bf16", 1), ("bf16", 3)):
         plan.search(echo, form, split, cells=cells[:1])
         _sync()
         t0 = time.perf_counter()

@@ -187,3 +187,40 @@ def test_config3_cfar_on_full_map():
     assert cnt == int(hit.sum()) and len(peaks) == cnt
     got = np.stack([peaks["coarse"].astype(np.int64), peaks["row"].astype(np.int64)], 1)
     assert np.array_equal(got, np.argwhere(hit))
+
+
+@pytest.mark.parametrize("form,split,tol", [("bf16_sym", 3, 1e-3), ("f16_sym", 1, 1e-3),
+                                            ("f32", 1, 1e-5)])
+def test_config5_full_map_on_target_window(form, split, tol):
+    """P = 3 at M=2048, N=8192: the full map (10^6 fine cells) of the first
+    target's coarse cell on an 8-row window around its range, element by
+    element on 2000 sampled fine cells plus each row's reported maximum,
+    against the oracle evaluated at those fine cells."""
+    from paper_2403_06788_amd.plan import Plan
+    case = synth.config_case(5)
+    c = synth.CONFIGS[5]
+    r = c["radar"]
+    tg = case["targets"][0]
+    n0 = int(round(tg.r0 / r.dr)) - 4
+    rows = (n0, n0 + 8)
+    plan = Plan(r.fc, r.fs, r.prf, c["M"], c["N"], c["order"], c["axes"], rows=rows)
+    grid = make_grid(Radar(r.fc, r.fs, r.prf), c["M"], c["N"], c["order"],
+                     [Axis(*a) for a in c["axes"]], *rows)
+    ks = []
+    for p, val in enumerate((tg.v, tg.a, tg.j)):
+        k = int(np.floor((val / plan.step[p] - plan.i_lo[p] + 0.5) / plan.R))
+        ks.append(min(max(k, 0), plan.K[p] - 1))
+    kt = (ks[2] * plan.K[1] + ks[1]) * plan.K[0] + ks[0]
+    print(f"config 5 {form} x{split}: cell {kt}, rows {rows}", flush=True)
+    Pd = plan.search_full(torch.from_numpy(case["echo"]).cuda(), form, split,
+                          cc_begin=kt, n=1)[0].cpu().numpy().astype(np.float64)
+    assert Pd.shape == (8, grid.n_fine)
+    rng = np.random.default_rng(77)
+    probe = np.unique(np.concatenate([rng.choice(grid.n_fine, 2000, replace=False),
+                                      Pd.argmax(axis=1)]))
+    y = OT.dsgrft_cell(case["echo"].astype(np.complex128), grid, kt, fine=probe)
+    P = np.abs(y) ** 2
+    scale = P.max()
+    assert scale > 0.5 * Pd.max()
+    assert np.abs(Pd[:, probe] - P).max() <= tol * scale
+    plan.close()

@@ -50,3 +50,26 @@ def test_order3_units_across_batches():
     pa, fa = big.search(echo, "f16", 1, cells=cells)
     pb, fb = one.search(echo, "f16", 1, cells=cells)
     assert torch.equal(pa, pb) and torch.equal(fa, fb)
+
+
+def test_two_plans_on_two_streams():
+    """A plan is used by one stream at a time, but separate plans may run
+    concurrently: two plans searching on two streams at once give the
+    results of the same searches run one after the other, bit for bit."""
+    big, one, echo = _plans("td")
+    ref_a = big.search(echo, "f16_sym", 1)
+    ref_b = one.search(echo, "bf16_sym", 3)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.current_stream().synchronize()
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            a = big.search(echo, "f16_sym", 1)
+        with torch.cuda.stream(s2):
+            b = one.search(echo, "bf16_sym", 3)
+        outs.append((a, b))
+    torch.cuda.synchronize()
+    for a, b in outs:
+        assert torch.equal(a[0], ref_a[0]) and torch.equal(a[1], ref_a[1])
+        assert torch.equal(b[0], ref_b[0]) and torch.equal(b[1], ref_b[1])
