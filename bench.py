@@ -344,10 +344,16 @@ def main():
                     "unit": "GB/s", "frac": round(g1_b / g1_s / 1e9 / HBM_GBPS, 4),
                     "avg_launch_ms": round(g1_s * 1e3, 4), "bytes_per_launch": g1_b,
                     "launches": p1["gather_launches"],
+                    "traffic": (_recorded(args.form, args.split, "traffic") or {}).get(
+                        "gather_bytes_per_launch"),
                     "note": "one 16-cell batch at a time, nothing running beside it; algorithmic "
                             "bytes (8 B read per sample): the 32 MiB echo stays in the 256 MiB "
                             "Infinity Cache, so re-reads of it are not all DRAM traffic and frac "
                             "can exceed 1"}
+    if gather_alone["traffic"]:
+        # DRAM-side bytes of the same launch shape (rocprofv3 FETCH_SIZE + WRITE_SIZE)
+        gather_alone["traffic_gbps"] = round(gather_alone["traffic"] / g1_s / 1e9, 1)
+        gather_alone["traffic_frac"] = round(gather_alone["traffic"] / g1_s / 1e9 / HBM_GBPS, 4)
     log(f"fine kernel: {achieved:.1f} TFLOP/s ({achieved / peak:.1%} of {peak}); "
         f"gather {gather['achieved']:.0f} GB/s beside the fine search, "
         f"{gather_alone['achieved']:.0f} GB/s alone")
