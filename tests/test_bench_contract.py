@@ -21,3 +21,24 @@ def test_world_size_above_one_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")], capture_output=True,
                        text=True, timeout=120, cwd=ROOT, env=env)
     assert r.returncode == 2
+
+
+def test_golden_error_helper():
+    """The benchmark's accuracy check on the oracle golden: zero error and no
+    index mismatch for the golden's own values, and a planted power error and
+    a planted index outside the near-tie set are reported."""
+    import numpy as np
+    import bench
+    g = bench.load_golden()
+    if g is None:
+        return
+    pm = np.zeros((g["k"].max() + 1, g["r"].max() + 1), np.float64)
+    af = np.zeros(pm.shape, np.int32)
+    pm[g["k"], g["r"]] = g["p"]
+    af[g["k"], g["r"]] = g["f"]
+    e, bad = bench.golden_error(pm, af, g)
+    assert e == 0.0 and bad == 0
+    pm[g["k"][5], g["r"][5]] += 3e-3 * g["pmax"]
+    af[g["k"][7], g["r"][7]] = g["f"][7] + 5000
+    e, bad = bench.golden_error(pm, af, g)
+    assert abs(e - 3e-3) < 1e-9 and bad == 1

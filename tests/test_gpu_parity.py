@@ -173,3 +173,44 @@ def test_bf16_pairs_equal_the_unpaired_form(case, split, other):
     P = p.search_full(case["echo_dev"], "bf16_sym", split).cpu().numpy().astype(np.float64)
     Q = p.search_full(case["echo_dev"], *other).cpu().numpy().astype(np.float64)
     assert np.abs(P - Q).max() <= 1e-5 * Q.max()
+
+
+def test_lrt_sigma2_from_device_and_capacity(case):
+    """dsgrft_detect with sigma^2 read from device memory (the noise-power
+    estimate written on the same stream) lists the same detections as with
+    the same value given on the host; with a list shorter than the count the
+    call reports E_CAPACITY (the binding returns the first `cap` entries and
+    the true count), and invalid P_FA or sigma^2 are rejected."""
+    import ctypes as C
+    from paper_2403_06788_amd import _lib
+    from paper_2403_06788_amd._lib import DsgrftError
+    p, g = case["plan"], case["grid"]
+    pm, af = p.search(case["echo_dev"], "f32", 1)
+    s2_dev = p.noise_power(case["echo_dev"], as_tensor=True)
+    s2 = float(s2_dev.item())
+    pfa = 0.05
+    pk_d, cnt_d, best_d = p.detect(pm, af, pfa, s2_dev, cap=4096)
+    pk_h, cnt_h, best_h = p.detect(pm, af, pfa, s2, cap=4096)
+    assert cnt_d == cnt_h > 3 and np.array_equal(pk_d, pk_h)
+    assert np.array_equal(best_d, best_h)
+    g2 = p.threshold(s2, pfa)
+    assert g2 == OD.threshold(g.M, s2, pfa)
+    assert cnt_h == int((pm.cpu().numpy().astype(np.float64) > g2).sum())
+    # capacity: the C call returns E_CAPACITY with the true count
+    peaks = torch.empty((2, _lib.PEAK_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    hc = C.c_int32(-1)
+    st = _lib.lib().dsgrft_detect(p._h, C.c_void_p(pm.data_ptr()), C.c_void_p(af.data_ptr()),
+                                  None, 0, pm.shape[0], s2, None, pfa,
+                                  C.c_void_p(peaks.data_ptr()), 2, C.c_void_p(count.data_ptr()),
+                                  None, C.byref(hc),
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 5 and hc.value == cnt_h == int(count.item())
+    got = peaks.cpu().numpy().view(_lib.PEAK_DTYPE).reshape(-1)
+    assert np.array_equal(got, pk_h[:2])
+    pk2, cnt2, _ = p.detect(pm, af, pfa, s2, cap=2)
+    assert cnt2 == cnt_h and len(pk2) == 2
+    for bad_pfa, bad_s2 in ((0.0, s2), (1.0, s2), (float("nan"), s2), (pfa, -1.0),
+                            (pfa, float("inf"))):
+        with pytest.raises(DsgrftError, match="invalid"):
+            p.detect(pm, af, bad_pfa, bad_s2)
