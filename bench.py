@@ -371,7 +371,9 @@ def main():
     log(f"oracle rows: {len(s_cells)} cells x {len(s_rows)} rows in {time.perf_counter() - t:.1f} s")
     forms = {}
     err, bad, clear, scale = sampled_error(pm_main, af_main, ref, s_rows, 1e-3)
-    gold = load_golden()
+    # the golden holds the oracle's time-domain (nearest-bin) map; the
+    # frequency-domain compensation computes a different map
+    gold = load_golden() if args.mgift == "td" else None
     gerr, gbad = golden_error(pm_main, af_main, gold)
     forms[f"{args.form}x{args.split}"] = {"cells_pulses_per_s": value, "ms": round(ms, 2),
                                          "steps": args.steps, "rel_err": err,

@@ -100,6 +100,27 @@ def test_kt_reduced_map_matches_oracle(kcase):
     near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), kcase["P"], TOL)
 
 
+@pytest.mark.parametrize("Np", [4096, 8192, 16384])
+def test_kt_rows_every_large_transform_length(Np):
+    """The compensation + IFFT kernel at N' = 4096, 8192 and 16384 (radix
+    plans 16/16/16, 32/16/16 and 64/16/16) against the oracle's rows."""
+    c = dict(KT_CASES["m64"])
+    c["N"] = Np * 3 // 4
+    g = _grid(c)
+    assert OF.pad_length(g) == Np
+    rng = np.random.default_rng(Np)
+    e = (rng.standard_normal((c["M"], c["N"])) +
+         1j * rng.standard_normal((c["M"], c["N"]))).astype(np.complex64)
+    p = _plan(c)
+    assert p.fd_pad == Np
+    y = p.mgift(torch.from_numpy(e).cuda()).cpu().numpy()
+    ee = e.astype(np.complex128)
+    SK = KT.keystone(OF.range_spectrum(ee, Np), g, Np)
+    ref = np.stack([KT.coarse_rows(ee, g, k, SK, Np) for k in range(KT.lattice(g).n_coarse)])
+    assert y.shape == ref.shape
+    assert np.abs(y - ref).max() <= TOL * np.abs(ref).max()
+
+
 def test_kt_cell_list_matches_range(kcase):
     p = kcase["plan"]
     cells = torch.tensor([p.n_coarse - 1, 0, p.n_coarse // 2], dtype=torch.int64)
