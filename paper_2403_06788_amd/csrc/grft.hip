@@ -11,9 +11,9 @@
 // offset lo and largest hi over the group.  The fine cells of a coarse cell
 // walk within about a bin of its centre, so at one pulse a group's offsets
 // nearly always fall in one or two bins: a thread loads the samples of its
-// rows at each bin of [lo, hi] once (the one at lo a pulse ahead) and every
-// cell takes the load of its own bin, rather than one load per cell; the
-// phasors are wave-uniform LDS reads.  Each cell's sum takes the same
+// rows at each bin of [lo, hi] once and every cell takes the load of its own
+// bin, rather than one load per cell; the group's phasors of a pulse are
+// read together, as wave-uniform LDS values, before its FMAs.  Each cell's sum takes the same
 // samples in the same order with the same FMAs as a direct evaluation (a
 // sample past the echo's ends is zero).
 #include "internal.h"
@@ -105,10 +105,6 @@ __global__ __launch_bounds__(256, 4) void k_grft(
     }
     __syncthreads();
     const int mc = (M - m0) < MC ? (M - m0) : MC;
-    // wc: the samples at the current pulse's smallest offset, loaded a pulse
-    // ahead
-    float2 wc[RPT];
-    window(wc, echo + (int64_t)m0 * N, __builtin_amdgcn_readfirstlane(s_lo[0]));
     for (int mm = 0; mm < mc; ++mm) {
       // lane l holds the offset of (pulse mm - mm % PG + l / FG, cell l % FG)
       const int offl = s_off[(mm / PG) * 64 + lane];
@@ -116,37 +112,34 @@ __global__ __launch_bounds__(256, 4) void k_grft(
       const float2 *row = echo + (int64_t)(m0 + mm) * N;
       const int lo = __builtin_amdgcn_readfirstlane(s_lo[mm]);
       const int hi = __builtin_amdgcn_readfirstlane(s_hi[mm]);
-      float2 wn[RPT];
-      const int mn = mm + 1 < mc ? mm + 1 : mm;
-      window(wn, echo + (int64_t)(m0 + mn) * N, __builtin_amdgcn_readfirstlane(s_lo[mn]));
-      {
-        // one pass per bin in [lo, hi], each cell in the pass of its offset
-        for (int b = lo; b <= hi; ++b) {
-          const unsigned in =
-              (unsigned)(__builtin_amdgcn_ballot_w64(lane / FG == mm % PG && offl == b) >> l0) &
-              all;
-          float2 w[RPT];
-          if (b == lo) {
+      float2 wc[RPT];
+      window(wc, row, lo);
+      float2 ph[FG];
 #pragma unroll
-            for (int j = 0; j < RPT; ++j) w[j] = wc[j];
-          } else {
-            window(w, row, b);
-          }
+      for (int q = 0; q < FG; ++q) ph[q] = s_ph[mm * FG + q];
+      // one pass per bin in [lo, hi], each cell in the pass of its offset
+      for (int b = lo; b <= hi; ++b) {
+        const unsigned in =
+            (unsigned)(__builtin_amdgcn_ballot_w64(lane / FG == mm % PG && offl == b) >> l0) &
+            all;
+        float2 w[RPT];
+        if (b == lo) {
 #pragma unroll
-          for (int q = 0; q < FG; ++q) {
-            if ((in >> q) & 1u) {
-              const float2 ph = s_ph[mm * FG + q];
+          for (int j = 0; j < RPT; ++j) w[j] = wc[j];
+        } else {
+          window(w, row, b);
+        }
 #pragma unroll
-              for (int j = 0; j < RPT; ++j) {
-                acc[q][j].x = fmaf(w[j].x, ph.x, fmaf(-w[j].y, ph.y, acc[q][j].x));
-                acc[q][j].y = fmaf(w[j].x, ph.y, fmaf(w[j].y, ph.x, acc[q][j].y));
-              }
+        for (int q = 0; q < FG; ++q) {
+          if ((in >> q) & 1u) {
+#pragma unroll
+            for (int j = 0; j < RPT; ++j) {
+              acc[q][j].x = fmaf(w[j].x, ph[q].x, fmaf(-w[j].y, ph[q].y, acc[q][j].x));
+              acc[q][j].y = fmaf(w[j].x, ph[q].y, fmaf(w[j].y, ph[q].x, acc[q][j].y));
             }
           }
         }
       }
-#pragma unroll
-      for (int j = 0; j < RPT; ++j) wc[j] = wn[j];
     }
     __syncthreads();
   }
