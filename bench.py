@@ -24,25 +24,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DS-GRFT cells·pulses/s (M=1024); MFMA vs FP32 speedup at rel err≤1e-3"
 PEAK_TFLOPS = {"f16": 2500.0, "f16_3m": 2500.0, "f16_sym": 2500.0, "bf16": 2500.0,
-               "bf16_glo": 2500.0, "bf16_sym": 2500.0, "fp8": 5000.0, "f32": 157.3,
-               "f32fft": 157.3}
+               "bf16_glo": 2500.0, "bf16_sym": 2500.0, "fp8": 5000.0, "fp8_sym": 5000.0,
+               "f32": 157.3, "f32fft": 157.3}
 DTYPE = {"f16_3m": "f16", "f16_sym": "f16", "f32fft": "f32", "bf16_glo": "bf16",
-         "bf16_sym": "bf16"}
+         "bf16_sym": "bf16", "fp8_sym": "fp8"}
 KERNEL = {"f16_3m": "k_fine_mfma3 (f16, three real products per complex product)",
           "f16_sym": "k_fine_mfma_sym<f16> (f16, fine cells in conjugate pairs, four real "
                      "products per pair)",
           "bf16_sym": "k_fine_mfma_sym<bf16> (bf16 split parts over conjugate pairs of fine "
-                      "cells, four real products per pair and part)"}
+                      "cells, four real products per pair and part)",
+          "fp8_sym": "k_fine_mfma_sym8 (e4m3 split parts over conjugate pairs of fine cells, "
+                     "four real products per pair and part)"}
 FORM_TEXT = {"f16_3m": "f16 MFMA, three real products per complex product (Gauss), split 1, "
                        "FP32 accumulation",
              "f16_sym": "f16 MFMA, fine cells in conjugate pairs (four real products for the "
                         "cells at +d and -d), split 1, FP32 accumulation",
              "bf16_sym": "bf16 MFMA over conjugate pairs of fine cells, split parts Fh Gh + Fh Gl "
                          "(+ Fl Gh for split 3), FP32 accumulation",
+             "fp8_sym": "e4m3 MFMA with block scales over conjugate pairs of fine cells, split "
+                        "parts Fh Gh + Fl Gh + Fh Gl (+ Fl Gl for split 4), FP32 accumulation",
              "f32fft": "FP32, fine velocities by slow-time FFT"}
 SWEEP = (("f16_sym", 1), ("f16_3m", 1), ("f16", 1), ("f16", 2), ("f16", 3), ("f16", 4),
          ("bf16_sym", 2), ("bf16_sym", 3), ("bf16", 1), ("bf16", 2), ("bf16_glo", 2),
-         ("bf16", 3), ("bf16", 4), ("fp8", 1), ("fp8", 2), ("fp8", 3), ("fp8", 4),
+         ("bf16", 3), ("bf16", 4), ("fp8_sym", 3), ("fp8_sym", 4), ("fp8", 1), ("fp8", 2),
+         ("fp8", 3), ("fp8", 4),
          ("f32fft", 1))
 SWEEP_STEPS = 3
 HBM_GBPS = 8000.0

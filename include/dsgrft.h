@@ -103,12 +103,17 @@ typedef enum {
                               Fi Gr of the +d column give both cells.  Same
                               operands and rounding as F16 split 1; not for
                               DS-KT-MFP plans */
-  DSGRFT_FORM_BF16_SYM = 8 /* bf16 over the conjugate pairs of F16_SYM,
+  DSGRFT_FORM_BF16_SYM = 8, /* bf16 over the conjugate pairs of F16_SYM,
                               split 2: Fh Gh + Fh Gl (the products of
                               BF16_GLO), split 3: + Fl Gh (those of BF16
                               split 3); every part accumulates into the same
                               four real products of a pair; not for
                               DS-KT-MFP plans */
+  DSGRFT_FORM_FP8_SYM = 9  /* e4m3 over the conjugate pairs of F16_SYM with
+                              the operands and block scales of FP8, split 3
+                              (Fh Gh + Fl Gh + Fh Gl) or 4 (+ Fl Gl), every
+                              part into the same four real products of a
+                              pair; not for DS-KT-MFP plans */
 } dsgrft_form;
 
 typedef struct {

@@ -19,7 +19,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "out of device memory",
           5: "output capacity exceeded"}
 
 FORMS = {"f32": 0, "f16": 1, "bf16": 2, "fp8": 3, "f32fft": 4, "f16_3m": 5, "bf16_glo": 6, "f16_sym": 7,
-         "bf16_sym": 8}
+         "bf16_sym": 8, "fp8_sym": 9}
 
 
 class DsgrftError(RuntimeError):

@@ -44,7 +44,7 @@ hipError_t dalloc(T **p, size_t bytes, size_t &total) {
 
 void release(dsgrft_plan p) {
   if (!p) return;
-  void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->FS16, p->FSB16, p->sym_cols, p->u_off, p->u_psi,
+  void *bufs[] = {p->F32, p->F16, p->FBF16, p->F8, p->FS16, p->FSB16, p->FS8, p->sym_cols, p->u_off, p->u_psi,
                   p->Gbuf[0], p->gscbuf[0], p->fft_tw, p->fd_tw, p->fd_spec, p->fd_E,
                   p->kt_spec, p->kt_invd, p->packed, p->det_ws, p->adj_ws, p->g_shift};
   for (void *b : bufs)
@@ -63,8 +63,8 @@ bool on_plan_device(dsgrft_plan p) {
 
 dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
   if (p->kt && form != DSGRFT_FORM_F32_FFT)
-    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_BF16_SYM) ? DSGRFT_E_UNSUPPORTED
-                                                                    : DSGRFT_E_INVALID;
+    return (form >= DSGRFT_FORM_F32 && form <= DSGRFT_FORM_FP8_SYM) ? DSGRFT_E_UNSUPPORTED
+                                                                   : DSGRFT_E_INVALID;
   switch (form) {
     case DSGRFT_FORM_F32:
       return split == 1 ? DSGRFT_OK : DSGRFT_E_INVALID;
@@ -78,6 +78,9 @@ dsgrft_status check_form(dsgrft_plan p, dsgrft_form form, int split) {
       return split == 2 ? DSGRFT_OK : DSGRFT_E_INVALID;
     case DSGRFT_FORM_BF16_SYM:
       return (split == 2 || split == 3) ? DSGRFT_OK : DSGRFT_E_INVALID;
+    case DSGRFT_FORM_FP8_SYM:
+      if (split != 3 && split != 4) return DSGRFT_E_INVALID;
+      return p->FS8 ? DSGRFT_OK : DSGRFT_E_UNSUPPORTED;
     case DSGRFT_FORM_F16:
     case DSGRFT_FORM_BF16:
     case DSGRFT_FORM_FP8:
@@ -93,7 +96,7 @@ double gather_bytes(dsgrft_form form, int split) {
   if (form == DSGRFT_FORM_F32 || form == DSGRFT_FORM_F32_FFT) return 8.0;
   const double planes =
       (split >= 3 || form == DSGRFT_FORM_BF16_GLO || form == DSGRFT_FORM_BF16_SYM) ? 4.0 : 2.0;
-  return planes * (form == DSGRFT_FORM_FP8 ? 1.0 : 2.0);
+  return planes * ((form == DSGRFT_FORM_FP8 || form == DSGRFT_FORM_FP8_SYM) ? 1.0 : 2.0);
 }
 
 // Executed MFMA flops per gathered unit of a fine-search launch: padded rows
@@ -108,7 +111,8 @@ double mfma_flops_per_unit(dsgrft_plan p, dsgrft_form form, int split) {
     case DSGRFT_FORM_BF16_GLO: prod = 8.0; break;
     case DSGRFT_FORM_F16_3M: prod = 3.0; break;
     case DSGRFT_FORM_F16_SYM: prod = 4.0; cols = 32.0 * p->FBs; break;
-    case DSGRFT_FORM_BF16_SYM: prod = 4.0 * split; cols = 32.0 * p->FBs; break;
+    case DSGRFT_FORM_BF16_SYM:
+    case DSGRFT_FORM_FP8_SYM: prod = 4.0 * split; cols = 32.0 * p->FBs; break;
     default: return 0.0;
   }
   return (double)p->rows_p * cols * (double)p->Mp * 2.0 * prod;
@@ -431,6 +435,8 @@ dsgrft_status dsgrft_plan_create(const dsgrft_radar *radar,
       dalloc(&p->F8, f16b ? (size_t)4 * p->Cp * p->Mp : 0, tot) != hipSuccess ||
       dalloc(&p->FS16, (size_t)2 * p->FBs * p->KB * 64 * sizeof(uint4), tot) != hipSuccess ||
       dalloc(&p->FSB16, (size_t)4 * p->FBs * p->KB * 64 * sizeof(uint4), tot) != hipSuccess ||
+      dalloc(&p->FS8, f16b ? (size_t)2 * p->FBs * p->KB * 64 * sizeof(uint4) : 0, tot) !=
+          hipSuccess ||
       dalloc(&p->sym_cols, 2 * sym_cols_n * sizeof(int32_t), tot) != hipSuccess ||
       dalloc(&p->gscbuf[0], 2 * (size_t)bu * p->rows_p * sizeof(int32_t), tot) != hipSuccess ||
       (fft_form_supported(M) &&

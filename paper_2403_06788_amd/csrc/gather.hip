@@ -343,7 +343,7 @@ hipError_t launch_gather_lp(dsgrft_plan p, dsgrft_form form, int split,
   // and in BF16_GLO and BF16_SYM
   const bool lo = split >= 3 || form == DSGRFT_FORM_BF16_GLO || form == DSGRFT_FORM_BF16_SYM;
   uint4 *G = (uint4 *)p->G;
-  if (form == DSGRFT_FORM_FP8) {
+  if (form == DSGRFT_FORM_FP8 || form == DSGRFT_FORM_FP8_SYM) {
     dim3 grid((unsigned)(nunits * p->NB));
     const size_t lds = (size_t)p->Mp * (sizeof(float2) + sizeof(int32_t));
     const bool staged = lds <= 48 * 1024;

@@ -78,6 +78,7 @@ struct dsgrft_plan_s {
   int FBs;              // column blocks of the conjugate-pair table (even)
   uint4 *FS16;          // its fp16 fragments, 2 planes (re, im) x FBs blocks
   uint4 *FSB16;         // the same columns in bf16, 4 planes (re/im hi, re/im lo)
+  uint4 *FS8;           // the same columns in e4m3, 4 planes (null without F8)
   int32_t *sym_cols;    // [2][FBs * 32]: fine cell of +d and of -d per
                         //   column (-1: none)
   int32_t *u_off;       // [batch_units][Mp] unit range offsets

@@ -92,20 +92,25 @@ __global__ void k_fine_tables(int M, int Mp, int C, int Cp, int R, int P, Lat L,
   }
 }
 
-// Conjugate-pair table: column c of block c / 32 holds the 16-bit fragments
-// of fine cell cols[c] (zero where cols[c] < 0), copied from the first
-// `planes` planes of F16 (fp16: re_hi, im_hi) or FBF16 (bf16: also re_lo,
-// im_lo).
+// Conjugate-pair table: column c of block c / 32 holds the fragments of
+// fine cell cols[c] (zero where cols[c] < 0), copied from the first `planes`
+// planes of F16 (fp16: re_hi, im_hi), FBF16 (bf16: also re_lo, im_lo) or F8
+// (e4m3, four planes).
+// HALVES 16-byte chunks per lane and fragment: 1 for the 16-bit tables, 2
+// for the e4m3 one (K blocks of 64 pulses, KB of them here).
 __global__ void k_sym_table(const uint4 *__restrict__ F16, const int32_t *__restrict__ cols,
-                            int FB, int FBs, int KB, int planes, uint4 *__restrict__ FS) {
+                            int FB, int FBs, int KB, int planes, int halves,
+                            uint4 *__restrict__ FS) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)planes * FBs * KB * 64) return;
-  const int lane = (int)(t & 63);
-  const int64_t q = t >> 6;
+  const int fr = 64 * halves;
+  if (t >= (int64_t)planes * FBs * KB * fr) return;
+  const int lane = (int)(t & 63), h = (int)((t >> 6) % halves);
+  const int64_t q = t / fr;
   const int kb = (int)(q % KB), cb = (int)((q / KB) % FBs), plane = (int)(q / ((int64_t)KB * FBs));
   const int f = cols[cb * 32 + (lane & 31)];
   FS[t] = f < 0 ? make_uint4(0u, 0u, 0u, 0u)
-                : F16[(((int64_t)plane * FB + (f >> 5)) * KB + kb) * 64 + (f & 31) + 32 * (lane >> 5)];
+                : F16[(((int64_t)plane * FB + (f >> 5)) * KB + kb) * fr + h * 64 + (f & 31) +
+                      32 * (lane >> 5)];
 }
 
 __global__ void k_unit_tables(const int64_t *cells, int64_t cc_base,
@@ -168,9 +173,14 @@ hipError_t launch_fine_tables(dsgrft_plan p, hipStream_t s) {
 hipError_t launch_sym_table(dsgrft_plan p, hipStream_t s) {
   const int64_t n = (int64_t)2 * p->FBs * p->KB * 64;
   hipLaunchKernelGGL(k_sym_table, dim3(blocks(n, 256)), dim3(256), 0, s, p->F16,
-                     p->sym_cols, p->FB, p->FBs, p->KB, 2, p->FS16);
+                     p->sym_cols, p->FB, p->FBs, p->KB, 2, 1, p->FS16);
   hipLaunchKernelGGL(k_sym_table, dim3(blocks(2 * n, 256)), dim3(256), 0, s, p->FBF16,
-                     p->sym_cols, p->FB, p->FBs, p->KB, 4, p->FSB16);
+                     p->sym_cols, p->FB, p->FBs, p->KB, 4, 1, p->FSB16);
+  // e4m3: 4 planes x KB / 4 blocks x 128 chunks = n chunks
+  if (p->FS8)
+    hipLaunchKernelGGL(k_sym_table, dim3(blocks(n, 256)), dim3(256), 0, s,
+                       (const uint4 *)p->F8, p->sym_cols, p->FB, p->FBs, p->KB / 4, 4, 2,
+                       p->FS8);
   return hipGetLastError();
 }
 

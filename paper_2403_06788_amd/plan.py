@@ -117,7 +117,8 @@ class Plan:
         (fine cells in conjugate pairs, four real products per pair) with
         split 1; "bf16_glo" (the gathered rows split) with split 2;
         "bf16_sym" over conjugate pairs with split 2 (bf16_glo's products)
-        or 3 (bf16 split 3's products)."""
+        or 3 (bf16 split 3's products); "fp8_sym" over conjugate pairs with
+        split 3 or 4 (fp8's products)."""
         echo = _echo(echo)
         if cells is not None:
             cells = cells.to(device="cuda", dtype=torch.int64).contiguous()

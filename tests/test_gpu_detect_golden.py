@@ -38,10 +38,11 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 FORMS = {
     2: [("f32", 1, 1e-5), ("f32fft", 1, 1e-5), ("f16_sym", 1, 1e-3), ("f16", 1, 1e-3),
         ("bf16_sym", 3, 1e-3), ("bf16", 3, 1e-3), ("bf16_sym", 2, 2e-3),
-        ("bf16_glo", 2, 2e-3), ("fp8", 3, 1e-3)],
+        ("bf16_glo", 2, 2e-3), ("fp8", 3, 1e-3), ("fp8_sym", 3, 1e-3)],
     3: [("f32fft", 1, 1e-5), ("f16_sym", 1, 1e-3), ("f16_3m", 1, 1e-3), ("f16", 1, 1e-3),
         ("bf16_sym", 3, 1e-3), ("bf16", 3, 1e-3), ("bf16_sym", 2, 2e-3),
-        ("bf16_glo", 2, 2e-3), ("bf16", 2, 2e-3), ("fp8", 3, 1e-3), ("fp8", 4, 1e-3)],
+        ("bf16_glo", 2, 2e-3), ("bf16", 2, 2e-3), ("fp8", 3, 1e-3), ("fp8", 4, 1e-3),
+        ("fp8_sym", 3, 1e-3), ("fp8_sym", 4, 1e-3)],
 }
 
 _cache = {}

@@ -12,7 +12,7 @@ from oracle.grid import Axis, Radar, make_grid
 pytestmark = pytest.mark.gpu
 
 FORMS = [("f32", 1, 1e-5), ("f16", 1, 1e-3), ("f16_3m", 1, 1e-3), ("f16_sym", 1, 1e-3), ("bf16", 3, 1e-4),
-         ("fp8", 3, 1e-2), ("bf16_glo", 2, 1e-2), ("bf16_sym", 3, 1e-4)]
+         ("fp8", 3, 1e-2), ("bf16_glo", 2, 1e-2), ("bf16_sym", 3, 1e-4), ("fp8_sym", 3, 1e-2)]
 
 # (fc, fs, prf, M, N, order, axes): one pulse and one bin; two pulses; a
 # single coarse cell of order 2 (zero-width acceleration axis) over 5 bins
@@ -82,7 +82,7 @@ def test_single_impulse_every_form():
     # takes the four-product form's operands and products (4u).
     bound = {"f32": 1e-6, "f16": 4 * 2.0 ** -11, "f16_3m": 12 * 2.0 ** -11, "f16_sym": 4 * 2.0 ** -11,
              "bf16_glo": 4 * 2.0 ** -8,
-             "bf16": 1e-4, "bf16_sym": 1e-4, "fp8": 8 * 2.0 ** -8}
+             "bf16": 1e-4, "bf16_sym": 1e-4, "fp8": 8 * 2.0 ** -8, "fp8_sym": 8 * 2.0 ** -8}
     for form, split, _ in FORMS:
         P = p.search_full(torch.from_numpy(echo).cuda(), form, split).cpu().numpy()
         assert np.array_equal(P == 0.0, ref == 0.0), (form, split)

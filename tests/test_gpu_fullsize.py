@@ -49,7 +49,8 @@ def _check_rows(pm, af, echo, grid, cells, rows, tol):
                                             ("f16_3m", 1, 1e-3), ("bf16_glo", 2, 1e-3),
                                             ("f16_sym", 1, 1e-3), ("bf16_sym", 3, 1e-3),
                                             ("bf16_sym", 2, 1e-3), ("bf16", 2, 1e-3),
-                                            ("fp8", 3, 1e-3), ("fp8", 4, 1e-3)])
+                                            ("fp8", 3, 1e-3), ("fp8", 4, 1e-3),
+                                            ("fp8_sym", 3, 1e-3), ("fp8_sym", 4, 1e-3)])
 def test_config3_full_search_sampled(form, split, tol):
     case, plan, grid, echo = _setup(3)
     pm, af = plan.search(echo, form, split)

@@ -208,6 +208,17 @@ def test_bf16_pairs_equal_the_unpaired_form(case, split, other):
     assert np.abs(P - Q).max() <= 1e-5 * Q.max()
 
 
+@pytest.mark.parametrize("split", [3, 4])
+def test_fp8_pairs_equal_the_unpaired_form(case, split):
+    """The conjugate-pair e4m3 form takes the operands, block scales and
+    products of the unpaired e4m3 form with the same split, so the two full
+    maps agree up to FP32 accumulation order (1e-5 of the peak)."""
+    p = case["plan"]
+    P = p.search_full(case["echo_dev"], "fp8_sym", split).cpu().numpy().astype(np.float64)
+    Q = p.search_full(case["echo_dev"], "fp8", split).cpu().numpy().astype(np.float64)
+    assert np.abs(P - Q).max() <= 1e-5 * Q.max()
+
+
 def test_lrt_sigma2_from_device_and_capacity(case):
     """dsgrft_detect with sigma^2 read from device memory (the noise-power
     estimate written on the same stream) lists the same detections as with

@@ -30,7 +30,8 @@ def _plans(mgift, order=2, M=128, N=300, axes=((-1500.0, 1500.0), (-400.0, 400.0
 
 @pytest.mark.parametrize("mgift,form,split", [("td", "f16", 1), ("td", "bf16", 3), ("td", "f16_3m", 1),
                                               ("td", "f16_sym", 1), ("td", "bf16_sym", 3),
-                                              ("td", "bf16_sym", 2), ("fd", "f16", 1),
+                                              ("td", "bf16_sym", 2), ("td", "fp8_sym", 3),
+                                              ("fd", "f16", 1),
                                               ("kt", "f32fft", 1)])
 def test_single_unit_batches_match_default_batching(mgift, form, split):
     big, one, echo = _plans(mgift)

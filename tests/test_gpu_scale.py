@@ -15,7 +15,7 @@ from oracle import transforms as OT
 pytestmark = pytest.mark.gpu
 
 FORMS = [("f32", 1), ("f16", 1), ("f16", 3), ("f16_3m", 1), ("f16_sym", 1), ("bf16", 3),
-         ("bf16_sym", 3), ("fp8", 3)]
+         ("bf16_sym", 3), ("fp8", 3), ("fp8_sym", 3)]
 
 
 @pytest.fixture(scope="module")
