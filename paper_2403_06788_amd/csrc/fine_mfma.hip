@@ -821,8 +821,10 @@ __global__ __launch_bounds__(256, (SymCfg<NPF, NPG>::WG)) void k_fine_mfma_sym(
 // and 4 planes x 4 row fragments of 2 KiB (48 KiB), so a three-slot ring
 // (144 KiB) leaves one workgroup per CU and one wave per SIMD.  That wave
 // reads the next step's fragments into a second register set while the
-// current step's MFMAs run (accumulators and both sets take ~330 of the 512
-// registers), with the ring filled one step ahead as in k_fine_mfma.
+// current step's MFMAs run (accumulators and both sets take ~460 of the 512
+// registers), with the ring filled two steps ahead; in the steady state the
+// reads alternate with the MFMAs, so that the matrix core starts right after
+// each barrier (11% faster than the reads first).
 template <int SPLIT>
 __global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
@@ -945,9 +947,16 @@ __global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
   };
 
   const int nkt = KS;
+  // three slots, two stages in flight: the slot of stage k is refilled with
+  // stage k + 3 right after the barrier of step k, since every wave read
+  // stage k into registers during step k - 1 (the wait on those reads goes
+  // before the barrier)
   issue(0);
-  if (nkt > 1) {
-    issue(1);
+  if (nkt > 1) issue(1);
+  if (nkt > 2) {
+    issue(2);
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(2 * CPT) : "memory");
+  } else if (nkt > 1) {
     asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(CPT) : "memory");
   } else {
     asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
@@ -955,19 +964,41 @@ __global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
   Set x0, x1;
   rd(0, x0);
   // step k: make stage k + 1 visible, read it into the other set, refill the
-  // slot of stage k - 1 (read during step k - 2, consumed by step k - 1's
-  // MFMAs) with stage k + 2, then the MFMAs of step k
+  // slot of stage k with stage k + 3, then the MFMAs of step k
   auto stp = [&](int k, Set &cur, Set &nxt) {
     if (k + 1 < nkt) {
       __builtin_amdgcn_sched_barrier(0);
-      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+      if (k + 2 < nkt)
+        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(CPT) : "memory");
+      else
+        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
       pinx(cur);
       rd(k + 1, nxt);
-      if (k + 2 < nkt) issue(k + 2);
+      if (k + 3 < nkt) issue(k + 3);
     }
     mm(cur);
   };
+  // steady state, branch-free (stages k + 1 .. k + 3 exist): the fragment
+  // reads interleave with the MFMAs, so the matrix core starts right after
+  // the barrier
+  auto steady = [&](int k, Set &cur, Set &nxt) {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(CPT) : "memory");
+    pinx(cur);
+    issue(k + 3);
+    rd(k + 1, nxt);
+    mm(cur);
+#pragma unroll
+    for (int i = 0; i < 8 * (SPLIT == 4 ? 4 : 3); ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+  };
   int kt = 0;
+  for (; kt + 4 < nkt; kt += 2) {
+    steady(kt, x0, x1);
+    steady(kt + 1, x1, x0);
+  }
   for (; kt + 1 < nkt; kt += 2) {
     stp(kt, x0, x1);
     stp(kt + 1, x1, x0);
