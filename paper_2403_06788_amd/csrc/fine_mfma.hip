@@ -816,25 +816,26 @@ __global__ __launch_bounds__(256, (SymCfg<NPF, NPG>::WG)) void k_fine_mfma_sym(
 // split 4: + Fl Gl), every part into the same four real products of a pair
 // with the block scales of the unpaired e4m3 form (fine table 2^-8 / 2^-12,
 // one code per gathered row and its lo part 2^-4 below).  Tile as
-// k_fine_mfma_sym (64 pair columns x 128 rows, one column block x two row
-// blocks per wave) with 64-pulse K steps; a stage holds 4 planes x 2 column
-// and 4 planes x 4 row fragments of 2 KiB (48 KiB), so a three-slot ring
-// (144 KiB) leaves one workgroup per CU and one wave per SIMD.  That wave
-// reads the next step's fragments into a second register set while the
-// current step's MFMAs run (accumulators and both sets take ~460 of the 512
-// registers), with the ring filled two steps ahead; in the steady state the
-// reads alternate with the MFMAs, so that the matrix core starts right after
-// each barrier (11% faster than the reads first).
+// k_fine_mfma_sym (64 pair columns x 128 rows) with 64-pulse K steps; a stage
+// holds 4 planes x 2 column and 4 planes x 4 row fragments of 2 KiB (48 KiB),
+// so a three-slot ring (144 KiB) leaves one workgroup per CU.  Eight waves,
+// one column block x one row block each (64 accumulator registers, 141 in
+// all), make two waves per SIMD: the MFMAs of one cover the fragment reads of
+// the other, which a single wave per SIMD with two register sets (two row
+// blocks per wave, ~460 registers) could not do as well (4.7 ms against
+// 3.6 ms per launch at M = 1024).  The ring is filled two steps ahead.
 template <int SPLIT>
-__global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
+__global__ __launch_bounds__(512, 1) void k_fine_mfma_sym8(
     const uint4 *__restrict__ F, const uint4 *__restrict__ G,
     const int32_t *__restrict__ gsc, int fsc, const int32_t *__restrict__ cols,
     unsigned long long *__restrict__ packed, float *__restrict__ full, int FBs, int NB,
     int KS, int rows_p, int64_t nunits, int64_t unit0, int R3, int C, int rows, int GN) {
   using Op = OpF8;
   constexpr int FR = 2, NP = 4, NBG = 4, NFB = 2, NST = 3;
+  constexpr int NTH = 64 * NFB * NBG;             // one wave per column x row block
   constexpr int NFR = NP * NFB + NP * NBG;        // 24 fragments per stage
-  constexpr int CH = NFR * FR * 64, CPT = CH / 256;  // 3072 chunks, 12 per thread
+  constexpr int CH = NFR * FR * 64, CPT = CH / NTH;  // 3072 chunks, 6 per thread
+  static_assert(CH % NTH == 0, "stage must split evenly over the workgroup");
   __shared__ uint4 lds[NST][CH];
 
   const int NT = NB / NBG, FT = FBs / NFB;
@@ -843,15 +844,11 @@ __global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
   const int wf = wave & 1, wn = wave >> 1;
   const int wbase = tid & ~63;
 
-  // row scale codes (hi; lo is 4 below) of this lane's two row blocks
-  int sb[2][2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
-    sb[0][j] = gsc[tm.u * rows_p + n];
-    asm volatile("" : "+v"(sb[0][j]));
-    sb[1][j] = sb[0][j] - 4;
-  }
+  // this lane's row and its scale codes (hi; lo is 4 below)
+  const int n = (tm.nt * NBG + wn) * 32 + (lane & 31);
+  int sbh = gsc[tm.u * rows_p + n];
+  asm volatile("" : "+v"(sbh));
+  const int sb[2] = {sbh, sbh - 4};
   const int sa[2] = {fsc, fsc - 4};
 
   // chunk c of a stage: lane c % 64, half (c / 64) % 2, fragment (c / 64) / 2:
@@ -860,7 +857,7 @@ __global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
   const uint4 *src[CPT];
 #pragma unroll
   for (int j = 0; j < CPT; ++j) {
-    const int c = tid + 256 * j;
+    const int c = tid + NTH * j;
     const int ln = c & 63, h = (c >> 6) % FR, fi = (c >> 6) / FR;
     if (fi < NP * NFB) {
       const int plane = fi / NFB, blk = fi % NFB;
@@ -876,7 +873,7 @@ __global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
 #pragma unroll
     for (int j = 0; j < CPT; ++j) {
       const unsigned la = __builtin_amdgcn_readfirstlane(
-          (unsigned)(size_t)(lds_void *)&dst[wbase + 256 * j]);
+          (unsigned)(size_t)(lds_void *)&dst[wbase + NTH * j]);
       const uint4 *g = src[j] + (int64_t)stage * (FR * 64);
       unsigned saved_m0;
       asm volatile(
@@ -892,156 +889,87 @@ __global__ __launch_bounds__(256, 1) void k_fine_mfma_sym8(
     }
   };
 
-  f16v acc[4][2];  // Prr, Pii, Pri, Pir per row block
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[q][j] = f16v{};
+  f16v acc[4] = {};  // Prr, Pii, Pri, Pir
 
   // fragments of one K step: f[plane] (re_hi, im_hi, re_lo, im_lo) of the
-  // wave's column block, g[plane][j] of its two row blocks
-  struct Set {
-    Frag<2> f[NP];
-    Frag<2> g[NP][2];
-  };
-  auto rd = [&](int kt, Set &x) {
+  // wave's column block, g[plane] of its row block
+  Frag<2> f[NP], g[NP];
+  auto rd = [&](int kt) {
     const uint4 *slot = lds[kt % NST];
 #pragma unroll
     for (int pl = 0; pl < NP; ++pl)
 #pragma unroll
-      for (int h = 0; h < FR; ++h) x.f[pl].v[h] = slot[((pl * NFB + wf) * FR + h) * 64 + lane];
-#pragma unroll
-    for (int pl = 0; pl < NP; ++pl)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int h = 0; h < FR; ++h)
-          x.g[pl][j].v[h] =
-              slot[((NP * NFB + pl * NBG + wn * 2 + j) * FR + h) * 64 + lane];
+      for (int h = 0; h < FR; ++h) {
+        f[pl].v[h] = slot[((pl * NFB + wf) * FR + h) * 64 + lane];
+        g[pl].v[h] = slot[((NP * NFB + pl * NBG + wn) * FR + h) * 64 + lane];
+      }
   };
-  auto pinx = [&](Set &x) {
-#pragma unroll
-    for (int pl = 0; pl < NP; ++pl) pin1<2>(x.f[pl]);
-#pragma unroll
-    for (int pl = 0; pl < NP; ++pl)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) pin1<2>(x.g[pl][j]);
+  // one product part: fine planes (pf, pf + 1) at scale la, row planes
+  // (pg, pg + 1) at scale lb
+  auto part = [&](int pf, int pg, int la, int lb) {
+    const int A = sa[la], B = sb[lb];
+    acc[0] = Op::mma(f[pf], g[pg], acc[0], A, B);
+    acc[1] = Op::mma(f[pf + 1], g[pg + 1], acc[1], A, B);
+    acc[2] = Op::mma(f[pf], g[pg + 1], acc[2], A, B);
+    acc[3] = Op::mma(f[pf + 1], g[pg], acc[3], A, B);
   };
-  // one product part: fine planes (fr, fi) at scale la, row planes (gr, gi)
-  // at scale lb
-  auto part = [&](const Set &x, int pf, int pg, int la, int lb) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int A = sa[la], B = sb[lb][j];
-      acc[0][j] = Op::mma(x.f[pf], x.g[pg][j], acc[0][j], A, B);
-      acc[1][j] = Op::mma(x.f[pf + 1], x.g[pg + 1][j], acc[1][j], A, B);
-      acc[2][j] = Op::mma(x.f[pf], x.g[pg + 1][j], acc[2][j], A, B);
-      acc[3][j] = Op::mma(x.f[pf + 1], x.g[pg][j], acc[3][j], A, B);
-    }
-  };
-  auto mm = [&](const Set &x) {
-    part(x, 0, 0, 0, 0);                 // Fh Gh
-    part(x, 2, 0, 1, 0);                 // Fl Gh
-    part(x, 0, 2, 0, 1);                 // Fh Gl
-    if (SPLIT == 4) part(x, 2, 2, 1, 1);  // Fl Gl
+  auto mm = [&]() {
+    part(0, 0, 0, 0);                 // Fh Gh
+    part(2, 0, 1, 0);                 // Fl Gh
+    part(0, 2, 0, 1);                 // Fh Gl
+    if (SPLIT == 4) part(2, 2, 1, 1);  // Fl Gl
   };
 
+  // three slots, stages k + 1 and k + 2 in flight during step k: the slot
+  // that stage k + 2 fills held stage k - 1, which every wave read (and
+  // waited for) before the barrier of step k
   const int nkt = KS;
-  // three slots, two stages in flight: the slot of stage k is refilled with
-  // stage k + 3 right after the barrier of step k, since every wave read
-  // stage k into registers during step k - 1 (the wait on those reads goes
-  // before the barrier)
   issue(0);
   if (nkt > 1) issue(1);
-  if (nkt > 2) {
-    issue(2);
-    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(2 * CPT) : "memory");
-  } else if (nkt > 1) {
-    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(CPT) : "memory");
-  } else {
-    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
-  }
-  Set x0, x1;
-  rd(0, x0);
-  // step k: make stage k + 1 visible, read it into the other set, refill the
-  // slot of stage k with stage k + 3, then the MFMAs of step k
-  auto stp = [&](int k, Set &cur, Set &nxt) {
-    if (k + 1 < nkt) {
-      __builtin_amdgcn_sched_barrier(0);
-      if (k + 2 < nkt)
-        asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(CPT) : "memory");
-      else
-        asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-      pinx(cur);
-      rd(k + 1, nxt);
-      if (k + 3 < nkt) issue(k + 3);
-    }
-    mm(cur);
-  };
-  // steady state, branch-free (stages k + 1 .. k + 3 exist): the fragment
-  // reads interleave with the MFMAs, so the matrix core starts right after
-  // the barrier
-  auto steady = [&](int k, Set &cur, Set &nxt) {
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(CPT) : "memory");
-    pinx(cur);
-    issue(k + 3);
-    rd(k + 1, nxt);
-    mm(cur);
-#pragma unroll
-    for (int i = 0; i < 8 * (SPLIT == 4 ? 4 : 3); ++i) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-    }
-  };
   int kt = 0;
-  for (; kt + 4 < nkt; kt += 2) {
-    steady(kt, x0, x1);
-    steady(kt + 1, x1, x0);
+  for (; kt + 2 < nkt; ++kt) {
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(CPT) : "memory");
+    issue(kt + 2);
+    rd(kt);
+    mm();
   }
-  for (; kt + 1 < nkt; kt += 2) {
-    stp(kt, x0, x1);
-    stp(kt + 1, x1, x0);
+  for (; kt < nkt; ++kt) {
+    if (kt + 1 < nkt)
+      asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(CPT) : "memory");
+    else
+      asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    rd(kt);
+    mm();
   }
-  if (kt < nkt) stp(kt, x0, x1);
   // ---- epilogue: both cells of each column ---------------------------------
-  const int psh = 0;
   const int64_t ug = unit0 + tm.u;
   const int64_t cpos = ug / R3;
   const unsigned fbase = (unsigned)((ug % R3) * C);
   const int ncols = FBs * 32;
   const int cb0 = (tm.ft * NFB + wf) * 32 + 4 * (lane >> 5);
-  unsigned long long best[2] = {0ull, 0ull};
+  unsigned long long best = 0ull;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int col = cb0 + 8 * (r >> 2) + (r & 3);
     const int fp = cols[col], fm = cols[ncols + col];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
-      const float prr = acc[0][j][r], pii = acc[1][j][r];
-      const float pri = acc[2][j][r], pir = acc[3][j][r];
-      const float ar = prr - pii, ai = pri + pir;  // +d
-      const float br = prr + pii, bi = pri - pir;  // -d
-      const float pa = ldexpf(ar * ar + ai * ai, psh), pb = ldexpf(br * br + bi * bi, psh);
-      if (fp >= 0) {
-        const unsigned ff = fbase + (unsigned)fp;
-        best[j] = umax64(best[j], ((unsigned long long)__float_as_uint(pa) << 32) | (0xffffffffu - ff));
-        if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pa;
-      }
-      if (fm >= 0) {
-        const unsigned ff = fbase + (unsigned)fm;
-        best[j] = umax64(best[j], ((unsigned long long)__float_as_uint(pb) << 32) | (0xffffffffu - ff));
-        if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pb;
-      }
+    const float prr = acc[0][r], pii = acc[1][r];
+    const float pri = acc[2][r], pir = acc[3][r];
+    const float ar = prr - pii, ai = pri + pir;  // +d
+    const float br = prr + pii, bi = pri - pir;  // -d
+    const float pa = ar * ar + ai * ai, pb = br * br + bi * bi;
+    if (fp >= 0) {
+      const unsigned ff = fbase + (unsigned)fp;
+      best = umax64(best, ((unsigned long long)__float_as_uint(pa) << 32) | (0xffffffffu - ff));
+      if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pa;
+    }
+    if (fm >= 0) {
+      const unsigned ff = fbase + (unsigned)fm;
+      best = umax64(best, ((unsigned long long)__float_as_uint(pb) << 32) | (0xffffffffu - ff));
+      if (full != nullptr && n < rows) full[(cpos * rows + n) * (int64_t)(C * R3) + ff] = pb;
     }
   }
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int n = (tm.nt * NBG + wn * 2 + j) * 32 + (lane & 31);
-    const unsigned long long b = umax64(best[j], shfl_xor64(best[j], 32));
-    if (lane < 32 && n < rows) atomicMax(&packed[cpos * rows + n], b);
-  }
+  best = umax64(best, shfl_xor64(best, 32));
+  if (lane < 32 && n < rows) atomicMax(&packed[cpos * rows + n], best);
 }
 
 
@@ -1152,7 +1080,7 @@ hipError_t launch_fine_mfma(dsgrft_plan p, dsgrft_form form, int split,
         return hipErrorInvalidValue;
       const int64_t tiles = nunits * (p->NB / 4) * (p->FBs / 2);
 #define DS_SYM8(SP)                                                                        \
-  hipLaunchKernelGGL((k_fine_mfma_sym8<SP>), dim3((unsigned)tiles), dim3(256), 0, s,         \
+  hipLaunchKernelGGL((k_fine_mfma_sym8<SP>), dim3((unsigned)tiles), dim3(512), 0, s,         \
                      (const uint4 *)p->FS8, (const uint4 *)p->G, p->g_scale, 119,           \
                      p->sym_cols, p->packed, full, p->FBs, p->NB, p->Mp / OpF8::KSTEP,      \
                      p->rows_p, nunits, unit0, p->R3, p->C, p->rows, 4)
