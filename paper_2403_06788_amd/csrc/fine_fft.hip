@@ -143,8 +143,12 @@ __device__ inline void wave_lds_sync() {
 // V[k1][l2][k2a] in row 8 j + k2a (length 65) at 8 kq + l2; every access of
 // both is conflict-free (contiguous on one side, padded rows on the other).
 // FULL (RV = M, HV = M/2) maps bin k to u1 = k xor M/2 (one fine index per
-// bin, no range test).
-template <int P, int NW, bool FULL, bool WFULL>
+// bin, no range test).  PRUNE (HV <= M/8 and RV - HV <= M/8, as for the R =
+// 100 fine velocities of a DS-GRFT cell at M >= 512): every wanted bin has
+// k2b = 0 (bins below M/8) or k2b = 7 (bins from 7M/8), so pass 3 forms only
+// those two outputs of each 8-point transform, X0 = sum v and
+// X7 = sum v exp(-j 2 pi l2 / 8), and the power and range tests cover 2 of 8.
+template <int P, int NW, bool FULL, bool WFULL, bool PRUNE>
 __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
     const float2 *__restrict__ G, const float2 *__restrict__ chirp,
     const float2 *__restrict__ twM, unsigned long long *__restrict__ packed,
@@ -155,6 +159,8 @@ __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
   constexpr int ROW1 = 72, ROW2 = 65;
   constexpr int XS = P * ROW1;
   static_assert(P % 8 == 0 && P <= 32, "points per lane");
+  static_assert(!(FULL && PRUNE), "all bins or the outer eighths");
+  constexpr int NK = PRUNE ? 2 : 8;  // outputs per 8-point transform of pass 3
   __shared__ float2 s_tw[M];            // [k1][l] = W_M^(l k1)
   __shared__ float2 s_x[NW * XS];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -234,19 +240,39 @@ __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
       for (int l2 = 0; l2 < 8; ++l2) v[j][l2] = xb[(j * 8 + lo3) * ROW2 + 8 * kq + l2];
     }
     wave_lds_sync();
+    // pass 3; output e of transform j is bin k2b = kb(e)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) fft_reg<8>(v[j]);
+    for (int j = 0; j < NJ; ++j) {
+      if constexpr (PRUNE) {
+        constexpr float h = 0.70710678118654752f;  // sqrt(1/2)
+        float2 a[4], b[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          a[l] = make_float2(v[j][l].x + v[j][l + 4].x, v[j][l].y + v[j][l + 4].y);
+          b[l] = make_float2(v[j][l].x - v[j][l + 4].x, v[j][l].y - v[j][l + 4].y);
+        }
+        const float2 c = make_float2(b[1].x - b[3].x, b[1].y - b[3].y);
+        const float2 d = make_float2(b[1].x + b[3].x, b[1].y + b[3].y);
+        v[j][0] = make_float2((a[0].x + a[2].x) + (a[1].x + a[3].x),
+                              (a[0].y + a[2].y) + (a[1].y + a[3].y));
+        v[j][1] = make_float2(fmaf(h, c.x + d.y, b[0].x + b[2].y),
+                              fmaf(h, c.y - d.x, b[0].y - b[2].x));
+      } else {
+        fft_reg<8>(v[j]);
+      }
+    }
+    auto kb = [](int e) { return PRUNE ? 7 * e : e; };
     if (!direct && !fin) {
       float cm = 0.f;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
 #pragma unroll
-        for (int k2b = 0; k2b < 8; ++k2b) {
-          const float pw = fmaf(v[j][k2b].x, v[j][k2b].x, v[j][k2b].y * v[j][k2b].y);
+        for (int e = 0; e < NK; ++e) {
+          const float pw = fmaf(v[j][e].x, v[j][e].x, v[j][e].y * v[j][e].y);
           if (FULL) {
             cm = fmaxf(cm, pw);
           } else {
-            const int b = kq + 8 * j + P * (lo3 + 8 * k2b);
+            const int b = kq + 8 * j + P * (lo3 + 8 * kb(e));
             cm = ((b + HV) % M < RV) ? fmaxf(cm, pw) : cm;
           }
         }
@@ -259,9 +285,9 @@ __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
 #pragma unroll
-        for (int k2b = 0; k2b < 8; ++k2b) {
-          const int b = kq + 8 * j + P * (lo3 + 8 * k2b);
-          const float pw = fmaf(v[j][k2b].x, v[j][k2b].x, v[j][k2b].y * v[j][k2b].y);
+        for (int e = 0; e < NK; ++e) {
+          const int b = kq + 8 * j + P * (lo3 + 8 * kb(e));
+          const float pw = fmaf(v[j][e].x, v[j][e].x, v[j][e].y * v[j][e].y);
           for (int u1 = FULL ? (b ^ (M / 2)) : (b + HV) % M; u1 < RV; u1 += M) {
             const unsigned ff = fbase + (unsigned)(i2 * RV + u1);
             best = umax64(best, ((unsigned long long)__float_as_uint(pw) << 32) |
@@ -312,8 +338,14 @@ hipError_t launch_w(dsgrft_plan p, int64_t nunits, int64_t unit0, float *full,
   const int64_t blocks = nunits * (p->rows_p / NW);
   const int R2 = p->P >= 2 ? p->R : 1;
   const bool fullbins = p->S0 == p->M;
-  auto kern = fullbins ? (full ? k_fine_fft_w<P, NW, true, true> : k_fine_fft_w<P, NW, true, false>)
-                       : (full ? k_fine_fft_w<P, NW, false, true> : k_fine_fft_w<P, NW, false, false>);
+  const int M = 64 * P, hv = p->S0 / 2;
+  const bool prune = !fullbins && hv <= M / 8 && p->S0 - hv <= M / 8;
+  auto kern = fullbins ? (full ? k_fine_fft_w<P, NW, true, true, false>
+                               : k_fine_fft_w<P, NW, true, false, false>)
+              : prune  ? (full ? k_fine_fft_w<P, NW, false, true, true>
+                               : k_fine_fft_w<P, NW, false, false, true>)
+                       : (full ? k_fine_fft_w<P, NW, false, true, false>
+                               : k_fine_fft_w<P, NW, false, false, false>);
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * NW), 0, s, (const float2 *)p->G,
                      p->fft_chirp, p->fft_tw, p->packed, full, p->Mp, p->rows, p->rows_p,
                      p->S0, p->S0 / 2, R2, unit0, p->R3, p->C);
