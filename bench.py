@@ -309,12 +309,13 @@ def main():
     roofline = fine_roofline(plan, prof, args.form, args.split)
     # attainable matrix-core rate on random operands (power-limited clock)
     ceiling = {}
-    for fm in ("f16", "bf16"):
+    for fm in ("f16", "bf16", "fp8"):
         tf, ghz = Plan.mfma_probe(fm, 50.0)
         ceiling[fm] = {"tflops": round(tf, 1), "clock_ghz": round(ghz, 3),
                        "frac_of_published": round(tf / PEAK_TFLOPS[fm], 4)}
     log(f"MFMA probe (register-only, random operands): f16 {ceiling['f16']['tflops']} TFLOP/s "
-        f"at {ceiling['f16']['clock_ghz']} GHz, bf16 {ceiling['bf16']['tflops']} TFLOP/s")
+        f"at {ceiling['f16']['clock_ghz']} GHz, bf16 {ceiling['bf16']['tflops']} TFLOP/s, "
+        f"e4m3 {ceiling['fp8']['tflops']} TFLOP/s at {ceiling['fp8']['clock_ghz']} GHz")
     op = DTYPE.get(args.form, args.form)
     if "executed" in roofline and op in ceiling:
         roofline["attainable"] = dict(ceiling[op], note=(

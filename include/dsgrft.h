@@ -418,11 +418,14 @@ dsgrft_status dsgrft_profile_end(dsgrft_plan plan, dsgrft_profile *out);
  * of the method).  Under sustained matrix work on random data the chip runs
  * at a power-limited clock, below the one the published peak assumes.  This
  * runs a register-only loop of v_mfma_f32_32x32x16_f16 (form
- * DSGRFT_FORM_F16) or _bf16 (DSGRFT_FORM_BF16) on random operands (random
- * signs, mantissas and exponents in [2^-8, 2^1); each MFMA takes another
- * operand pair; no memory traffic) on the current device, for about `ms`
- * milliseconds after a warm-up, on the default stream, and waits for it.
- * *h_tflops receives the executed rate (32768 flops per MFMA) and *h_ghz
+ * DSGRFT_FORM_F16), _bf16 (DSGRFT_FORM_BF16) or
+ * v_mfma_scale_f32_32x32x64_f8f6f4 on e4m3 operands (DSGRFT_FORM_FP8) on
+ * random operands (random signs and mantissas; exponents in [2^-8, 2^1) for
+ * fp16 and bf16, in [2^-1, 2^8) for e4m3 with block scales 2^-8 and 2^-7;
+ * each MFMA takes another operand pair; no memory traffic) on the current
+ * device, for about `ms` milliseconds after a warm-up, on the default
+ * stream, and waits for it.  *h_tflops receives the executed rate (32768
+ * flops per 16-bit MFMA, 131072 per e4m3 MFMA) and *h_ghz
  * the mean shader clock the workgroups read while it ran.  Allocates two
  * small device buffers for its results (it is not an execution entry
  * point).  E_INVALID for another form, NULL outputs or ms outside

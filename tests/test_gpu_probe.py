@@ -1,11 +1,11 @@
 """The matrix-core probe used for the attainable roofline: a plausible rate
-(below the published peak) and shader clock, for fp16 and bf16."""
+(below the published peak) and shader clock, for fp16, bf16 and e4m3."""
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("form,peak", [("f16", 2500.0), ("bf16", 2500.0)])
+@pytest.mark.parametrize("form,peak", [("f16", 2500.0), ("bf16", 2500.0), ("fp8", 5000.0)])
 def test_mfma_probe_rate_and_clock(form, peak):
     from paper_2403_06788_amd.plan import Plan
     tf, ghz = Plan.mfma_probe(form, 20.0)
