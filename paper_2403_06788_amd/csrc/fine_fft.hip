@@ -176,6 +176,14 @@ __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
 #pragma unroll
   for (int k = 0; k < 8; ++k) t2[k] = twM[(P * (lane & 7) * k) & (M - 1)];
   __syncthreads();
+  // at M = 1024, this lane's W_M^(l k1) for k1 < NTR held in registers (all
+  // of them in the pruned variant, half in the all-bins one, as their
+  // registers allow at three waves per SIMD); the rest, and every twiddle at
+  // other M, read from LDS for every chirp
+  constexpr int NTR = P != 16 ? 0 : PRUNE ? P : FULL ? P / 2 : 0;
+  float2 t1[NTR > 0 ? NTR : 1];
+#pragma unroll
+  for (int k1 = 0; k1 < NTR; ++k1) t1[k1] = s_tw[k1 * 64 + lane];
 
   const int64_t ug = unit0 + u;
   const int64_t cpos = ug / R3;
@@ -214,7 +222,8 @@ __global__ __launch_bounds__(64 * NW) void k_fine_fft_w(
     fft_reg<P>(x);
 #pragma unroll
     for (int k1 = 0; k1 < P; ++k1) {
-      const float2 z = k1 ? cmulf(x[k1], s_tw[k1 * 64 + lane]) : x[0];
+      const float2 z = k1 ? cmulf(x[k1], k1 < NTR ? t1[k1 < NTR ? k1 : 0] : s_tw[k1 * 64 + lane])
+                          : x[0];
       xb[((k1 >> 3) * 8 + kq) * ROW1 + 8 * (k1 & 7) + lo3] = z;
     }
     wave_lds_sync();

@@ -14,7 +14,10 @@ pytestmark = pytest.mark.gpu
 
 # power-of-two M: P = 1 with M < R (aliased bins), P = 2 (two factorings of M),
 # P = 2 with a row window (wavefront-per-row kernel, 8 pulses per lane), P = 2
-# at M = 2048 (32 pulses per lane, two wavefronts per workgroup), P = 3
+# at M = 2048 (32 pulses per lane, two wavefronts per workgroup), P = 3.  The
+# wavefront kernel forms only the outer eighths of each transform when the R
+# wanted fine velocities fit there (R/2 <= M/8: the M >= 512 cases above);
+# p2m512wide (R = 150 > M/4) takes every bin of the last pass.
 FFT_CASES = {
     "p1alias": dict(fc=1.0e9, fs=1.0e7, prf=500.0, M=64, N=256, order=1,
                     axes=[(-150.0, 150.0)], targets=1, snr_db=0.0, rows=None),
@@ -25,6 +28,8 @@ FFT_CASES = {
                        rows=(40, 300)),
     "p2m2048": dict(fc=1.2e8, fs=1.0e7, prf=1000.0, M=2048, N=96, order=2,
                     axes=[(-20.0, 20.0), (-10.0, 10.0)], targets=2, snr_db=-10.0, rows=None),
+    "p2m512wide": dict(fc=1.5e9, fs=1.0e7, prf=1000.0, M=512, N=64, order=2,
+                       axes=[(-10.0, 10.0), (-5.0, 5.0)], targets=2, snr_db=-10.0, rows=None),
     "p3m64": dict(fc=6.0e7, fs=1.0e7, prf=500.0, M=64, N=200, order=3,
                   axes=[(-150.0, 150.0), (-600.0, 600.0), (-9000.0, 9000.0)],
                   targets=2, snr_db=-3.0, rows=None),
