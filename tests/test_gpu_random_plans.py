@@ -1,0 +1,84 @@
+"""Parity with the FP64 oracle on seeded random small plans: the DS-GRFT map
+(GFT eq. (44) after the mGIFT and pre-DFM of eqs. (46)-(47)) reduced over each
+cell's fine lattice (eq. (72)).  Order, R, PRF, pulse count, range bins, a row
+window and the motion extents (one to three coarse cells per axis) are drawn
+from a fixed seed, so the cases cover tile tails the hand-written cases do
+not; every main form's reduced map and argmax are checked under the near-tie
+rule at its tolerance (FP32 forms 1e-5, fp16 pairs 1e-3, bf16 pairs x3 1e-4,
+e4m3 pairs x3 1e-2 as for the other 8-bit small cases)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from cases import near_tie_check
+from oracle import transforms as OT
+from oracle.grid import Axis, Radar, make_grid
+
+pytestmark = pytest.mark.gpu
+
+FS = 1.0e7
+MAX_WORK = 1.5e9  # coarse cells x rows x fine cells x pulses of one oracle map
+
+
+def _draw(seed):
+    """One plan: (spec, grid) with its oracle work below MAX_WORK."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    while True:
+        order = int(rng.choice([1, 2, 2, 2, 3]))
+        R = int(rng.choice([6, 11, 12, 24, 100] if order < 3 else [5, 6, 8]))
+        fc = R * FS
+        prf = float(rng.choice([500.0, 1000.0]))
+        M = int(rng.choice([64, 72, 100, 128, 200, 256, 512, 512, 1024, 1024]))
+        N = int(rng.integers(40, 321))
+        rows = None
+        if rng.random() < 0.4:
+            a = int(rng.integers(0, N // 3))
+            rows = (a, int(rng.integers(a + 1, N + 1)))
+        radar = Radar(fc, FS, prf)
+        g0 = make_grid(radar, M, N, order, [Axis(0.0, 0.0)] * order)
+        axes = []
+        for q in range(order):
+            c = R * g0.steps[q] * float(rng.uniform(0.3, 2.6))
+            axes.append((-c, c * float(rng.uniform(0.5, 1.0))))
+        g = make_grid(radar, M, N, order, [Axis(*a) for a in axes],
+                      *(rows if rows else (0, None)))
+        work = float(g.n_coarse) * g.rows * g.n_fine * M
+        if work <= MAX_WORK:
+            spec = dict(fc=fc, prf=prf, M=M, N=N, order=order, axes=axes, rows=rows)
+            return spec, g
+
+
+SEEDS = list(range(2024, 2036))
+
+# (form, split, tolerance); the FFT form needs a power-of-two pulse count
+FORMS = [("f32", 1, 1e-5), ("f16_sym", 1, 1e-3), ("bf16_sym", 3, 1e-4),
+         ("fp8_sym", 3, 1e-2), ("f32fft", 1, 1e-5)]
+
+
+@pytest.fixture(scope="module", params=SEEDS)
+def rcase(request):
+    spec, g = _draw(request.param)
+    print(f"seed {request.param}: {spec}", flush=True)
+    radar = synth.RadarParams(spec["fc"], FS, spec["prf"])
+    rng = np.random.Generator(np.random.PCG64(request.param + 7))
+    axes = spec["axes"] + [(0.0, 0.0)] * (3 - spec["order"])
+    tg = synth.draw_targets(rng, radar, spec["M"], spec["N"], 2, -3.0, 1.0,
+                            axes[0], axes[1], axes[2])
+    echo = synth.make_echo(radar, spec["M"], spec["N"], tg, 1.0, rng)
+    from paper_2403_06788_amd.plan import Plan
+    p = Plan(spec["fc"], FS, spec["prf"], spec["M"], spec["N"], spec["order"], spec["axes"],
+             rows=spec["rows"])
+    assert (p.n_coarse, p.rows, p.n_fine) == (g.n_coarse, g.rows, g.n_fine)
+    return dict(spec=spec, plan=p, echo_dev=torch.from_numpy(echo).cuda(),
+                P=OT.dsgrft_power(echo.astype(np.complex128), g))
+
+
+@pytest.mark.parametrize("form,split,tol", FORMS)
+def test_random_plan_reduced_map(rcase, form, split, tol):
+    M = rcase["spec"]["M"]
+    if form == "f32fft" and (M & (M - 1)) != 0:
+        pytest.skip("the FFT form takes a power-of-two pulse count")
+    pm, af = rcase["plan"].search(rcase["echo_dev"], form, split)
+    err, _ = near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), rcase["P"], tol)
+    print(f"{form} x{split}: {err:.3e}", flush=True)
