@@ -8,7 +8,9 @@ rule at its tolerance (FP32 forms 1e-5, fp16 pairs 1e-3, bf16 pairs x3 1e-4,
 e4m3 pairs x3 1e-2 as for the other 8-bit small cases).  The same plans with
 the frequency-domain mGIFT (Alg. 1) are checked against oracle.fd, and those
 of order 2 with a power-of-two pulse count as DS-KT-MFP (Alg. 4, Prop. 3, FFT
-fine search) against oracle.ktmfp at 1e-5."""
+fine search) against oracle.ktmfp at 1e-5.  The LRT detections (eqs. (31),
+(33), Alg. 3) of the time-domain plans are compared with the oracle's at
+P_FA 1e-6 ... 1e-1 under the near-tie rule of the detection goldens."""
 import numpy as np
 import pytest
 import torch
@@ -81,7 +83,7 @@ def _case(seed, mgift):
         P = OF.dsgrft_fd_power(echo, g)
     else:
         P = KT.power(echo, g)
-    return dict(spec=spec, plan=p, echo_dev=torch.from_numpy(echo).cuda(), P=P)
+    return dict(spec=spec, plan=p, grid=g, echo_dev=torch.from_numpy(echo).cuda(), P=P)
 
 
 @pytest.fixture(scope="module", params=SEEDS)
@@ -126,3 +128,27 @@ def test_random_plan_reduced_map_ktmfp(rcase_kt):
     assert pm.shape[0] == rcase_kt["P"].shape[0]
     err, _ = near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), rcase_kt["P"], 1e-5)
     print(f"DS-KT-MFP: {err:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("form,split,tol", [("f32", 1, 1e-5), ("f16_sym", 1, 1e-3)])
+def test_random_plan_detections(rcase, form, split, tol):
+    """Detection list, global maximum and FP64 peak parameters against the
+    oracle's full map (every reduced entry with its near-tie fine cells).  A
+    detection's row is the absolute range bin n0 (the window start plus the
+    map row)."""
+    from test_gpu_detect_golden import _compare
+    P = rcase["P"]
+    n0 = rcase["grid"].n_begin
+    pm_ref, af_ref = P.max(axis=-1), P.argmax(axis=-1)
+    ents = {}
+    for k in range(P.shape[0]):
+        for r in range(P.shape[1]):
+            near = np.nonzero(P[k, r] >= 0.99 * pm_ref[k, r])[0]
+            ents[(k, n0 + r)] = [k, n0 + r, int(af_ref[k, r]), float(pm_ref[k, r]),
+                                 [[int(f), float(P[k, r, f])] for f in near
+                                  if f != af_ref[k, r]]]
+    order = sorted(ents.values(), key=lambda x: -x[3])
+    top = [[x[0], x[1], x[2], x[3]] for x in order[:64]]
+    pm, af = rcase["plan"].search(rcase["echo_dev"], form, split)
+    _compare(rcase["plan"], rcase["grid"], pm, af, ents, top, float(P.max()),
+             [1e-6, 1e-3, 1e-1], 1.0, tol)
