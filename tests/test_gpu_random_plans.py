@@ -10,13 +10,17 @@ the frequency-domain mGIFT (Alg. 1) are checked against oracle.fd, and those
 of order 2 with a power-of-two pulse count as DS-KT-MFP (Alg. 4, Prop. 3, FFT
 fine search) against oracle.ktmfp at 1e-5.  The LRT detections (eqs. (31),
 (33), Alg. 3) of the time-domain plans are compared with the oracle's at
-P_FA 1e-6 ... 1e-1 under the near-tie rule of the detection goldens."""
+P_FA 1e-6 ... 1e-1 under the near-tie rule of the detection goldens, and on
+the plans of order 1 and 2 the adjoint of the continuous objective (its value,
+theta gradient and echo gradient at random off-grid candidates) with
+oracle.adjoint."""
 import numpy as np
 import pytest
 import torch
 
 import synth
 from cases import near_tie_check
+from oracle import adjoint as OA
 from oracle import fd as OF
 from oracle import ktmfp as KT
 from oracle import transforms as OT
@@ -83,7 +87,8 @@ def _case(seed, mgift):
         P = OF.dsgrft_fd_power(echo, g)
     else:
         P = KT.power(echo, g)
-    return dict(spec=spec, plan=p, grid=g, echo_dev=torch.from_numpy(echo).cuda(), P=P)
+    return dict(spec=spec, plan=p, grid=g, echo=echo, echo_dev=torch.from_numpy(echo).cuda(),
+                P=P)
 
 
 @pytest.fixture(scope="module", params=SEEDS)
@@ -152,3 +157,29 @@ def test_random_plan_detections(rcase, form, split, tol):
     pm, af = rcase["plan"].search(rcase["echo_dev"], form, split)
     _compare(rcase["plan"], rcase["grid"], pm, af, ents, top, float(P.max()),
              [1e-6, 1e-3, 1e-1], 1.0, tol)
+
+
+def test_random_plan_adjoint(rcase):
+    """J, dJ/dtheta and dJ/ds at eight random candidates inside the plan's
+    extents against the FP64 oracle (tolerances of the adjoint tests)."""
+    spec, g = rcase["spec"], rcase["grid"]
+    if spec["order"] > 2:
+        pytest.skip("the adjoint's candidates are (r0, v, a)")
+    rng = np.random.default_rng(spec["N"])
+    n = 8
+    va = [spec["axes"][0], spec["axes"][1] if spec["order"] == 2 else (0.0, 0.0)]
+    th = np.stack([rng.uniform(2, g.N - 3, n) * g.dr,
+                   rng.uniform(*va[0], n), rng.uniform(*va[1], n)], axis=1)
+    plan = rcase["plan"]
+    J, saved = plan.adjoint_forward(rcase["echo_dev"], torch.from_numpy(th))
+    gJ = np.linspace(0.5, 2.0, n)
+    gt, ge = plan.adjoint_backward(rcase["echo_dev"], torch.from_numpy(th), saved,
+                                   torch.from_numpy(gJ))
+    J, gt, ge = J.cpu().numpy(), gt.cpu().numpy(), ge.cpu().numpy()
+    for b in range(n):
+        Jo, _, go, _ = OA.gradients(rcase["echo"], g, th[b])
+        assert J[b] == pytest.approx(Jo, rel=1e-9, abs=1e-9 * (Jo + 1))
+        np.testing.assert_allclose(gt[b], gJ[b] * go, rtol=1e-7,
+                                   atol=1e-9 * np.abs(gJ[b] * go).max())
+    _, _, ref = OA.batch(rcase["echo"], g, th, grad_J=gJ, want_echo_grad=True)
+    assert np.abs(ge - ref).max() <= 1e-5 * np.abs(ref).max()
