@@ -13,7 +13,8 @@ fine search) against oracle.ktmfp at 1e-5.  The LRT detections (eqs. (31),
 P_FA 1e-6 ... 1e-1 under the near-tie rule of the detection goldens, and on
 the plans of order 1 and 2 the adjoint of the continuous objective (its value,
 theta gradient and echo gradient at random off-grid candidates) with
-oracle.adjoint."""
+oracle.adjoint; the single-scale TD-GRFT (eq. (13)) of every plan, full and
+reduced map, at 1e-5."""
 import numpy as np
 import pytest
 import torch
@@ -183,3 +184,13 @@ def test_random_plan_adjoint(rcase):
                                    atol=1e-9 * np.abs(gJ[b] * go).max())
     _, _, ref = OA.batch(rcase["echo"], g, th, grad_J=gJ, want_echo_grad=True)
     assert np.abs(ge - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_random_plan_grft(rcase):
+    """TD-GRFT full map and reduced map against the oracle's eq. (13)."""
+    g = rcase["grid"]
+    pm, af, P = rcase["plan"].grft(rcase["echo_dev"], full=True)
+    ref = OT.grft_power(rcase["echo"].astype(np.complex128), g)
+    P = P.cpu().numpy().astype(np.float64)
+    assert np.abs(P - ref).max() / ref.max() <= 1e-5
+    near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), ref, 1e-5)
