@@ -14,7 +14,8 @@ P_FA 1e-6 ... 1e-1 under the near-tie rule of the detection goldens, and on
 the plans of order 1 and 2 the adjoint of the continuous objective (its value,
 theta gradient and echo gradient at random off-grid candidates) with
 oracle.adjoint; the single-scale TD-GRFT (eq. (13)) of every plan, full and
-reduced map, at 1e-5."""
+reduced map, at 1e-5; cell-averaging CFAR decisions bit for bit on the
+device's reduced map with a random window."""
 import numpy as np
 import pytest
 import torch
@@ -22,6 +23,7 @@ import torch
 import synth
 from cases import near_tie_check
 from oracle import adjoint as OA
+from oracle import detect as OD
 from oracle import fd as OF
 from oracle import ktmfp as KT
 from oracle import transforms as OT
@@ -194,3 +196,24 @@ def test_random_plan_grft(rcase):
     P = P.cpu().numpy().astype(np.float64)
     assert np.abs(P - ref).max() / ref.max() <= 1e-5
     near_tie_check(pm.cpu().numpy(), af.cpu().numpy(), ref, 1e-5)
+
+
+def test_random_plan_cfar(rcase):
+    """CA-CFAR along range on the fp16-pair device map: the oracle's
+    decisions on the same map, the listed powers and fine cells, and the
+    global maximum; guard, training length and alpha drawn per plan."""
+    g = rcase["grid"]
+    rng = np.random.default_rng(rcase["spec"]["N"] + 1)
+    guard, train = int(rng.integers(0, 4)), int(rng.integers(1, 24))
+    alpha = float(rng.uniform(1.2, 4.0))
+    pm, af = rcase["plan"].search(rcase["echo_dev"], "f16_sym", 1)
+    pm_h, af_h = pm.cpu().numpy(), af.cpu().numpy()
+    want = [(int(k), int(r)) for k, r in np.argwhere(OD.ca_cfar(pm_h, guard, train, alpha))]
+    peaks, cnt, best = rcase["plan"].detect_cfar(pm, af, guard, train, alpha, cap=1 << 20)
+    got = [(int(q["coarse"]), int(q["row"]) - g.n_begin) for q in peaks]
+    assert cnt == len(want) and got == want, (guard, train, alpha)
+    for q in peaks[:50]:
+        k, r = int(q["coarse"]), int(q["row"]) - g.n_begin
+        assert q["power"] == pm_h[k, r] and int(q["fine"]) == af_h[k, r]
+    kb, rb = np.unravel_index(np.argmax(pm_h), pm_h.shape)
+    assert (int(best["coarse"]), int(best["row"]) - g.n_begin) == (kb, rb)
