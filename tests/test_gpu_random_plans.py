@@ -15,7 +15,9 @@ the plans of order 1 and 2 the adjoint of the continuous objective (its value,
 theta gradient and echo gradient at random off-grid candidates) with
 oracle.adjoint; the single-scale TD-GRFT (eq. (13)) of every plan, full and
 reduced map, at 1e-5; cell-averaging CFAR decisions bit for bit on the
-device's reduced map with a random window."""
+device's reduced map with a random window; each form's full map within its
+tolerance of the oracle, its reduced map exactly the max / first argmax of
+that full map."""
 import numpy as np
 import pytest
 import torch
@@ -217,3 +219,19 @@ def test_random_plan_cfar(rcase):
         assert q["power"] == pm_h[k, r] and int(q["fine"]) == af_h[k, r]
     kb, rb = np.unravel_index(np.argmax(pm_h), pm_h.shape)
     assert (int(best["coarse"]), int(best["row"]) - g.n_begin) == (kb, rb)
+
+
+@pytest.mark.parametrize("form,split,tol", FORMS)
+def test_random_plan_full_map(rcase, form, split, tol):
+    """Full |Y|^2 map of each form against the oracle, and the reduced map as
+    its exact max and first argmax (both variants of a kernel round alike)."""
+    M = rcase["spec"]["M"]
+    if form == "f32fft" and (M & (M - 1)) != 0:
+        pytest.skip("the FFT form takes a power-of-two pulse count")
+    p = rcase["plan"]
+    P = p.search_full(rcase["echo_dev"], form, split).cpu().numpy()
+    ref = rcase["P"]
+    assert np.abs(P.astype(np.float64) - ref).max() <= tol * ref.max()
+    pm, af = p.search(rcase["echo_dev"], form, split)
+    assert np.array_equal(pm.cpu().numpy(), P.max(axis=-1))
+    assert np.array_equal(af.cpu().numpy(), P.argmax(axis=-1))
